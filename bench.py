@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Quartics height-classified per second at p = 7 on one MI355X.
+
+Workload (named in config.workload): the p = 7 batch of 65,536 seeded
+quartics of uneven structure from workloads.config_p7_batch (seed 0): half
+diagonal a x1^4 + b x2^4 + c x3^4 + d x4^4 plus 1-8 random cross terms, half
+dense, nonzero values uniform in {1..6}.  One step is one qfs_height call over
+the whole batch with the inputs already in HBM: Fedder's test for every
+surface, then Delta_1 on int8 matrix cores and the theta loop for the
+surfaces that fail it.
+
+Printed: one JSON line with the throughput, the roofline of the dominant
+kernel (the Delta_1 + theta kernel, timed live with hipEvents on its stream),
+the CPU oracle on a bounded sample of the same workload, and the plain
+per-surface GPU kernels on a sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+from math import comb
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "quartics height-classified/sec at p=7 (batched int8-MFMA vs plain), bit-exact"
+INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix peak, 5.0 POP/s
+
+
+def delta1_macs(p):
+    """Useful multiply-adds of the chain g~^(k+1) = g~^k * g~, k = 1..p-1 (dense schoolbook counts)."""
+    d = 4 * (p - 1)
+    return sum(comb(d * k + 3, 3) * comb(d + 3, 3) for k in range(1, p))
+
+
+def theta_macs(p, h, bound=10):
+    """theta work of one deep surface with height h: (tests) x len_g + (full maps) x len_g^2."""
+    lg = comb(4 * p - 1, 3)
+    if h == 0:
+        tests, full = bound - 1, bound - 2
+    else:
+        tests, full = h - 1, h - 2
+    return tests * lg + max(full, 0) * lg * lg
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="p7_batch65536")
+    ap.add_argument("--cpu-sample", type=int, default=384)
+    ap.add_argument("--plain-sample", type=int, default=48)
+    ap.add_argument("--no-baselines", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the height pipeline has no cross-GPU step and this build runs on a "
+              "single MI355X; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2502_12428_amd as qfs
+    import workloads
+
+    F, P = workloads.CONFIGS[args.workload]()
+    B = F.shape[0]
+    p = int(P.max())
+    f = torch.from_numpy(F).cuda()
+    pt = torch.from_numpy(P).cuda()
+    ws = qfs.Workspace()
+    print("bench: workload %s, batch %d, warmup %d, steps %d" % (args.workload, B, args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        h = qfs.height(f, pt, max_p=p, workspace=ws)
+    torch.cuda.synchronize()
+    qfs.profile_collect()
+    qfs.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        h = qfs.height(f, pt, max_p=p, workspace=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    qfs.profile(False)
+    stage_ms, calls = qfs.profile_collect()
+    elapsed = t1 - t0
+    heights = h.cpu().numpy()
+
+    parity = "unchecked"
+    gold = os.path.join(ROOT, "tests", "golden", "heights_%s.npz" % args.workload)
+    if os.path.exists(gold):
+        parity = bool(np.array_equal(np.load(gold)["heights"].astype(np.int32), heights))
+
+    deep_key = "deep_p%d" % p
+    deep_ms = stage_ms[deep_key] / max(calls, 1)
+    deep = heights[(heights == 0) | (heights >= 2)]
+    n_deep = int(deep.size)
+    useful = n_deep * delta1_macs(p) + sum(theta_macs(p, int(x)) for x in deep)
+    achieved = 2.0 * useful / (deep_ms * 1e-3) / 1e12 if deep_ms > 0 else 0.0
+    executed = 2.0 * n_deep * qfs.mfma_per_surface(p) * 16384 / (deep_ms * 1e-3) / 1e12 if deep_ms > 0 else 0.0
+    print("bench: %.1f ms/step, stages %s, deep surfaces %d" % (1e3 * elapsed / args.steps,
+          {k: round(v / max(calls, 1), 3) for k, v in stage_ms.items()}, n_deep), file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": B * args.steps / elapsed,
+        "unit": "quartics/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8",
+        "data": "synthetic",
+        "config": {"workload": "%s: p=%d, %d seeded quartics (half diagonal plus 1-8 cross terms, half dense; "
+                               "values uniform 1..6), bound 10" % (args.workload, p, B),
+                   "p": p, "batch": B, "bound": 10},
+        "parity_vs_oracle": parity,
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "k_deep<%d> (Delta_1 chain on v_mfma_i32_16x16x64_i8 + theta)" % p,
+            "achieved": achieved,
+            "peak": INT8_PEAK_TOPS,
+            "unit": "TOP/s",
+            "frac": achieved / INT8_PEAK_TOPS,
+            "traffic": None,
+            "kernel_ms_per_launch": deep_ms,
+            "useful_ops_per_launch": 2.0 * useful,
+            "deep_surfaces_per_launch": n_deep,
+            "executed_mfma_tops": executed,
+            "executed_mfma_frac": executed / INT8_PEAK_TOPS,
+        },
+        "stage_ms_per_step": {k: v / max(calls, 1) for k, v in stage_ms.items()},
+    }
+
+    if not args.no_baselines:
+        # plain per-surface GPU kernels on the first surfaces of the same workload
+        n = min(args.plain_sample, B)
+        hp = qfs.height_plain(f[:n], p)
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        hp = qfs.height_plain(f[:n], p)
+        torch.cuda.synchronize()
+        tp1 = time.perf_counter()
+        out["plain_baseline"] = {
+            "value": n / (tp1 - tp0), "unit": "quartics/s", "kind": "plain per-surface VALU kernels",
+            "sample": "first %d surfaces of %s" % (n, args.workload),
+            "agrees_with_batched": bool(np.array_equal(hp.cpu().numpy(), heights[:n])),
+        }
+        out["speedup_vs_plain"] = out["value"] / out["plain_baseline"]["value"]
+        # CPU oracle on a bounded sample, all host threads
+        from oracle import fast
+        n = min(args.cpu_sample, B)
+        threads = os.cpu_count() or 1
+        tc0 = time.perf_counter()
+        hc = fast.heights(F[:n], P[:n], threads=threads)
+        tc1 = time.perf_counter()
+        out["cpu_baseline"] = {
+            "value": n / (tc1 - tc0), "unit": "quartics/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d surfaces of %s, C oracle (oracle/qfs_oracle.c) on a thread pool" % (n, args.workload),
+            "agrees_with_gpu": bool(np.array_equal(hc, heights[:n])),
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,165 @@
+/*
+ * qfs.h -- C ABI of libqfs: quasi-F-split (Artin-Mazur) heights of quartic
+ * K3 surfaces over F_p on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Batubara, Garzella, Pan, "K3 surfaces of any Artin-Mazur height
+ * over F5 and F7 via quasi-F-split singularities and GPU acceleration"
+ * (arXiv 2502.12428).  For a quartic f in F_p[x1,x2,x3,x4]:
+ *   g     = f^(p-1) mod p                       (Algorithm 3, first line)
+ *   h = 1 if g is not in m^[p]                   (Fedder's criterion, Section 2.2)
+ *   Delta = Delta_1(g) = (g~^p - sum_t t^p)/p    (Algorithm 1, Section 3.1)
+ *   theta(a) = u(Delta * a)                      (Algorithm 2 and Section 3.4)
+ *   h = least k in 2..bound with theta^(k-1)(g) not in m^[p], else infinity
+ *                                                (Algorithm 3; Theorem C with h <= 10 for K3)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Coefficient arrays are uint8, one value in [0, p) per monomial, row-major
+ *   [batch][len].  A homogeneous form of degree n has len = C(n+3, 3)
+ *   monomials (Section 4, Lemma "wics size"), stored in descending
+ *   lexicographic order of the exponent tuple (e1,e2,e3,e4), x1 > x2 > x3 > x4
+ *   (the order the paper's tables print terms in).  The position of (e1..e4)
+ *   is qfs_monomial_rank(e) = C(e2+e3+e4+2,3) + C(e3+e4+1,2) + e4.
+ *   A quartic is 35 bytes; g has C(4p-1,3) bytes; Delta has C(4p(p-1)+3,3).
+ * - Supported primes: 3, 5, 7, 11.
+ * - Array arguments marked "device" are device pointers, allocated and owned
+ *   by the caller (e.g. the data_ptr() of a torch tensor).  The library never
+ *   allocates device memory: scratch comes from the caller's workspace `ws`,
+ *   which must be 256-byte aligned and hold at least the bytes reported by the
+ *   matching *_workspace_bytes() call; its contents need no initialisation
+ *   and are clobbered.
+ * - Calls are asynchronous on `stream` (0 = the null stream): they enqueue
+ *   kernels and return.  Argument errors are detected on the host before
+ *   anything is enqueued and are returned as a negative qfs_status; the text
+ *   is available from qfs_last_error() in the calling thread.
+ * - Calls that share a workspace must not overlap in time.
+ */
+#ifndef QFS_H
+#define QFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QFS_OK = 0,
+    QFS_EINVAL = -1,      /* bad argument (null pointer, size, bound, coefficient >= p) */
+    QFS_ENOMEM = -2,      /* workspace smaller than required */
+    QFS_EDEVICE = -3,     /* a HIP runtime call failed */
+    QFS_EUNSUPPORTED = -4,/* prime not in {3, 5, 7, 11} */
+    QFS_EARITH = -5       /* an internal exactness check failed (never expected) */
+} qfs_status;
+
+/* Height value meaning "infinite" (no height <= bound); finite heights are 1..bound. */
+#define QFS_HEIGHT_INF 0
+
+/* Number of monomials of degree deg in 4 variables: C(deg+3, 3); 0 if deg < 0. */
+int64_t qfs_num_monomials(int deg);
+
+/* Position of the exponent tuple e[0..3] (host pointer) in its degree's
+ * coefficient array (formula above); -1 if some exponent is negative. */
+int64_t qfs_monomial_rank(const int32_t e[4]);
+
+/* Inverse of qfs_monomial_rank for degree deg: writes e[0..3] (host pointer).
+ * Returns QFS_OK, or QFS_EINVAL if rank is outside [0, qfs_num_monomials(deg)). */
+int qfs_monomial_unrank(int deg, int64_t rank, int32_t e[4]);
+
+/* Coefficient counts for prime p: len of g = C(4p-1,3), len of Delta = C(4p(p-1)+3,3). */
+int64_t qfs_len_g(int p);
+int64_t qfs_len_delta(int p);
+
+/* ------------------------------------------------------------------------
+ * qfs_delta1 -- Algorithm 1 applied to g = f^(p-1) (Section 3.1,
+ * Proposition "delta1 formula"; Algorithm 3, lines 1 and 4).
+ *
+ *   f          device, [batch][35], values in [0,p): the quartics.
+ *   g_out      device, [batch][C(4p-1,3)] or NULL: receives g = f^(p-1) mod p.
+ *   delta_out  device, [batch][C(4p(p-1)+3,3)]: receives Delta_1(g) mod p,
+ *              with the sign of Algorithm 1: (g~^p - sum_t t^p)/p, where g~
+ *              lifts g with coefficients in [0,p) and t runs over its terms.
+ *   status_out device, [batch] int32 or NULL: per-surface QFS_OK, or
+ *              QFS_EINVAL if some coefficient of f is >= p (outputs of that
+ *              surface are then unspecified), or QFS_EARITH.
+ * g~^p is formed in Z/p^2 on int8 matrix cores with int32 accumulation; the
+ * Delta_1 division is exact and checked.
+ * Returns QFS_OK or a negative qfs_status (nothing enqueued on error).
+ * ---------------------------------------------------------------------- */
+size_t qfs_delta1_workspace_bytes(int p, int batch);
+int qfs_delta1(int p, int batch, const uint8_t *f, uint8_t *g_out, uint8_t *delta_out,
+               int32_t *status_out, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * qfs_theta -- iterate the "multiply then split" map theta(a) = u(Delta a)
+ * (Algorithm 2 applied to Delta*a; Section 3.4): out = theta^iters(a).
+ *
+ *   delta  device, [batch][C(4p(p-1)+3,3)], values in [0,p): Delta per surface.
+ *   a      device, [batch][C(4p-1,3)], values in [0,p): the starting forms.
+ *   out    device, [batch][C(4p-1,3)]: theta^iters(a); may not alias a.
+ *   iters  0..64 (0 copies a).
+ * Values >= p in delta or a are the caller's error; they are reduced mod p.
+ * ---------------------------------------------------------------------- */
+size_t qfs_theta_workspace_bytes(int p, int batch);
+int qfs_theta(int p, int batch, const uint8_t *delta, const uint8_t *a, uint8_t *out, int iters,
+              void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * qfs_height -- Algorithm 3 for a batch of quartics over possibly different
+ * primes, in one batched launch sequence (surfaces grouped by p; only those
+ * that fail Fedder's criterion run Delta_1 and theta).
+ *
+ *   batch    number of surfaces (0 is allowed and enqueues nothing).
+ *   p        device, [batch] int32: each surface's prime.
+ *   f        device, [batch][35], values in [0,p).
+ *   bound    1..10: the b of Algorithm 3 (10 for K3 surfaces).
+ *   max_p    the largest prime the batch may hold (3, 5, 7 or 11); it sizes
+ *            the workspace, and surfaces with a larger p are rejected.
+ *   heights  device, [batch] int32: 1..bound, QFS_HEIGHT_INF (0), or a
+ *            negative qfs_status for that surface (QFS_EUNSUPPORTED for a
+ *            prime outside {3,5,7,11} or above max_p, QFS_EINVAL for a
+ *            coefficient >= p, QFS_EARITH for a failed exactness check).
+ * The workspace must hold qfs_height_workspace_bytes(batch, max_p) bytes.
+ * ---------------------------------------------------------------------- */
+size_t qfs_height_workspace_bytes(int batch, int max_p);
+int qfs_height(int batch, const int32_t *p, const uint8_t *f, int bound, int max_p, int32_t *heights,
+               void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * qfs_height_plain -- the same heights for surfaces of one prime p, computed
+ * one surface at a time with plain vector-ALU kernels (no matrix cores, no
+ * batching): the comparison baseline for qfs_height.  Arguments as above.
+ * ---------------------------------------------------------------------- */
+size_t qfs_height_plain_workspace_bytes(int p);
+int qfs_height_plain(int p, int batch, const uint8_t *f, int bound, int32_t *heights,
+                     void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Stage timing (diagnostics).  While enabled, every qfs_height call records
+ * hipEvents on its stream around its stages; qfs_profile_collect waits for
+ * the recorded events, writes the summed milliseconds per stage into ms[0..5]
+ * (0 stage 1, 1 plans, 2..5 deep kernels for p = 3, 5, 7, 11) and the number
+ * of calls into *calls, and clears the record.  Host pointers.
+ * ---------------------------------------------------------------------- */
+int qfs_profile_enable(int on);
+int qfs_profile_collect(double ms[6], int *calls);
+
+/* Matrix-core instructions (v_mfma_i32_16x16x64_i8, 16,384 multiply-adds
+ * each) that the Delta_1 product issues for one surface at prime p; the
+ * count depends only on p.  -1 for an unsupported p. */
+int64_t qfs_mfma_per_surface(int p);
+
+/* Message for the last error returned in the calling thread ("" if none). */
+const char *qfs_last_error(void);
+
+/* Releases host-side caches; the library holds no device memory. */
+void qfs_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QFS_H */

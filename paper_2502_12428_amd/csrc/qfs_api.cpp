@@ -1,0 +1,357 @@
+// Host side of the libqfs C ABI (include/qfs.h): argument checks, workspace
+// layouts and the launch sequences.  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/qfs.h"
+#include "qfs_internal.h"
+
+using namespace qfs;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+bool supported(int p) { return prime_index(p) >= 0; }
+
+int device_cus()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return n;
+}
+
+bool aligned(const void *p) { return ((uintptr_t)p & 255u) == 0; }
+
+// ---- stage timing: hipEvents recorded on the caller's stream ----
+struct ProfRec {
+    hipEvent_t ev[10];
+    int stage[10];  // stage index of the interval ending at ev[i] (-1: none)
+    int n;
+};
+struct Prof {
+    std::mutex m;
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<ProfRec> recs;
+    hipEvent_t get()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+} g_prof;
+
+struct ProfCall {
+    ProfRec r{};
+    bool on;
+    hipStream_t s;
+    explicit ProfCall(hipStream_t st) : on(false), s(st)
+    {
+        std::lock_guard<std::mutex> lk(g_prof.m);
+        on = g_prof.on;
+        r.n = 0;
+    }
+    void mark(int stage)
+    {
+        if (!on || r.n >= 10) return;
+        hipEvent_t e;
+        {
+            std::lock_guard<std::mutex> lk(g_prof.m);
+            e = g_prof.get();
+        }
+        if (!e) return;
+        hipEventRecord(e, s);
+        r.ev[r.n] = e;
+        r.stage[r.n] = stage;
+        r.n++;
+    }
+    ~ProfCall()
+    {
+        if (!on || r.n == 0) return;
+        std::lock_guard<std::mutex> lk(g_prof.m);
+        g_prof.recs.push_back(r);
+    }
+};
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(QFS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t qfs_num_monomials(int deg) { return num_mono(deg); }
+
+int64_t qfs_monomial_rank(const int32_t e[4])
+{
+    if (!e || e[0] < 0 || e[1] < 0 || e[2] < 0 || e[3] < 0) return -1;
+    return cns_rank(e[1], e[2], e[3]);
+}
+
+int qfs_monomial_unrank(int deg, int64_t rank, int32_t e[4])
+{
+    if (!e || deg < 0 || rank < 0 || rank >= num_mono(deg))
+        return fail(QFS_EINVAL, "qfs_monomial_unrank: rank %lld outside [0, %lld)", (long long)rank,
+                    (long long)num_mono(deg));
+    int a, b, c, d;
+    cns_unrank(deg, rank, a, b, c, d);
+    e[0] = a;
+    e[1] = b;
+    e[2] = c;
+    e[3] = d;
+    return QFS_OK;
+}
+
+int64_t qfs_len_g(int p) { return supported(p) ? num_mono(4 * (p - 1)) : -1; }
+int64_t qfs_len_delta(int p) { return supported(p) ? num_mono(4 * p * (p - 1)) : -1; }
+
+const char *qfs_last_error(void) { return g_err; }
+
+void qfs_shutdown(void) {}
+
+// ---------------------------------------------------------------------------
+size_t qfs_delta1_workspace_bytes(int p, int batch)
+{
+    if (!supported(p) || batch < 0) return 0;
+    bool present[4] = {false, false, false, false};
+    present[prime_index(p)] = true;
+    return make_batch_layout(present, batch, device_cus()).total;
+}
+
+int qfs_delta1(int p, int batch, const uint8_t *f, uint8_t *g_out, uint8_t *delta_out, int32_t *status_out,
+               void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    g_err[0] = 0;
+    if (!supported(p)) return fail(QFS_EUNSUPPORTED, "qfs_delta1: p=%d not in {3,5,7,11}", p);
+    if (batch < 0) return fail(QFS_EINVAL, "qfs_delta1: batch=%d < 0", batch);
+    if (batch == 0) return QFS_OK;
+    if (!f || !delta_out || !ws) return fail(QFS_EINVAL, "qfs_delta1: null pointer argument");
+    if (!aligned(ws)) return fail(QFS_EINVAL, "qfs_delta1: workspace not 256-byte aligned");
+    const int ncu = device_cus();
+    if (ncu <= 0) return fail(QFS_EDEVICE, "qfs_delta1: no HIP device");
+    bool present[4] = {false, false, false, false};
+    const int pi = prime_index(p);
+    present[pi] = true;
+    const BatchLayout L = make_batch_layout(present, batch, ncu);
+    if (ws_bytes < L.total)
+        return fail(QFS_ENOMEM, "qfs_delta1: workspace %zu bytes < %zu needed", ws_bytes, L.total);
+    uint8_t *w = (uint8_t *)ws;
+    int32_t *counters = (int32_t *)(w + L.counters);
+    hipError_t e;
+    if ((e = launch_reset(counters, stream)) != hipSuccess) return hip_fail(e, "reset");
+    Stage1Args s1{};
+    s1.batch = batch;
+    s1.mode = MODE_DELTA;
+    s1.fixed_p = p;
+    s1.bound = 10;
+    s1.f = f;
+    s1.status = status_out;
+    s1.g_out = g_out;
+    s1.counters = counters;
+    for (int i = 0; i < 4; ++i) {
+        s1.queue[i] = L.present[i] ? (int32_t *)(w + L.queue[i]) : nullptr;
+        s1.gq[i] = L.present[i] ? w + L.gq[i] : nullptr;
+    }
+    s1.present_mask = 1 << pi;
+    if ((e = launch_stage1(s1, p, stream)) != hipSuccess) return hip_fail(e, "stage1");
+    if ((e = launch_plan(p, (uint32_t *)(w + L.plan[pi]), stream)) != hipSuccess) return hip_fail(e, "plan");
+    DeepArgs da{};
+    da.mode = MODE_DELTA;
+    da.bound = 10;
+    da.status = status_out;
+    da.delta_out = delta_out;
+    da.counters = counters;
+    da.queue = (const int32_t *)(w + L.queue[pi]);
+    da.gq = w + L.gq[pi];
+    da.plan = (const uint32_t *)(w + L.plan[pi]);
+    da.slots = w + L.slots;
+    da.slot_bytes = L.slot_stride[pi];
+    const int nslots = batch < L.nslots[pi] ? batch : L.nslots[pi];
+    if ((e = launch_deep(p, da, nslots, stream)) != hipSuccess) return hip_fail(e, "deep");
+    return QFS_OK;
+}
+
+// ---------------------------------------------------------------------------
+size_t qfs_theta_workspace_bytes(int p, int batch)
+{
+    if (!supported(p) || batch < 0) return 0;
+    const int ncu = device_cus();
+    const int slots = batch < ncu ? batch : ncu;
+    return (size_t)(slots > 0 ? slots : 1) * theta_scratch_bytes(p);
+}
+
+int qfs_theta(int p, int batch, const uint8_t *delta, const uint8_t *a, uint8_t *out, int iters, void *ws,
+              size_t ws_bytes, hipStream_t stream)
+{
+    g_err[0] = 0;
+    if (!supported(p)) return fail(QFS_EUNSUPPORTED, "qfs_theta: p=%d not in {3,5,7,11}", p);
+    if (batch < 0) return fail(QFS_EINVAL, "qfs_theta: batch=%d < 0", batch);
+    if (iters < 0 || iters > 64) return fail(QFS_EINVAL, "qfs_theta: iters=%d outside 0..64", iters);
+    if (batch == 0) return QFS_OK;
+    if (!delta || !a || !out || !ws) return fail(QFS_EINVAL, "qfs_theta: null pointer argument");
+    if (out == a) return fail(QFS_EINVAL, "qfs_theta: out aliases a");
+    if (!aligned(ws)) return fail(QFS_EINVAL, "qfs_theta: workspace not 256-byte aligned");
+    const int ncu = device_cus();
+    if (ncu <= 0) return fail(QFS_EDEVICE, "qfs_theta: no HIP device");
+    const size_t need = qfs_theta_workspace_bytes(p, batch);
+    if (ws_bytes < need) return fail(QFS_ENOMEM, "qfs_theta: workspace %zu bytes < %zu needed", ws_bytes, need);
+    const int slots = batch < ncu ? batch : ncu;
+    hipError_t e = launch_theta(p, batch, delta, a, out, iters, (uint8_t *)ws, slots, stream);
+    if (e != hipSuccess) return hip_fail(e, "theta");
+    return QFS_OK;
+}
+
+// ---------------------------------------------------------------------------
+static void present_upto(int max_p, bool present[4])
+{
+    for (int i = 0; i < 4; ++i) present[i] = kPrimes[i] <= max_p;
+}
+
+size_t qfs_height_workspace_bytes(int batch, int max_p)
+{
+    if (batch < 0 || max_p < 3 || max_p > 11) return 0;
+    bool present[4];
+    present_upto(max_p, present);
+    return make_batch_layout(present, batch, device_cus()).total;
+}
+
+int qfs_height(int batch, const int32_t *p, const uint8_t *f, int bound, int max_p, int32_t *heights, void *ws,
+               size_t ws_bytes, hipStream_t stream)
+{
+    g_err[0] = 0;
+    if (batch < 0) return fail(QFS_EINVAL, "qfs_height: batch=%d < 0", batch);
+    if (bound < 1 || bound > 10) return fail(QFS_EINVAL, "qfs_height: bound=%d outside 1..10", bound);
+    if (max_p < 3 || max_p > 11 || !supported(max_p))
+        return fail(QFS_EUNSUPPORTED, "qfs_height: max_p=%d not in {3,5,7,11}", max_p);
+    if (batch == 0) return QFS_OK;
+    if (!p || !f || !heights || !ws) return fail(QFS_EINVAL, "qfs_height: null pointer argument");
+    if (!aligned(ws)) return fail(QFS_EINVAL, "qfs_height: workspace not 256-byte aligned");
+    const int ncu = device_cus();
+    if (ncu <= 0) return fail(QFS_EDEVICE, "qfs_height: no HIP device");
+    bool present[4];
+    present_upto(max_p, present);
+    const BatchLayout L = make_batch_layout(present, batch, ncu);
+    if (ws_bytes < L.total)
+        return fail(QFS_ENOMEM, "qfs_height: workspace %zu bytes < %zu needed", ws_bytes, L.total);
+    uint8_t *w = (uint8_t *)ws;
+    int32_t *counters = (int32_t *)(w + L.counters);
+    hipError_t e;
+    ProfCall prof(stream);
+    prof.mark(-1);
+    if ((e = launch_reset(counters, stream)) != hipSuccess) return hip_fail(e, "reset");
+    Stage1Args s1{};
+    s1.batch = batch;
+    s1.mode = MODE_HEIGHT;
+    s1.fixed_p = 0;
+    s1.bound = bound;
+    s1.p = p;
+    s1.f = f;
+    s1.heights = heights;
+    s1.counters = counters;
+    int mask = 0;
+    for (int i = 0; i < 4; ++i) {
+        s1.queue[i] = L.present[i] ? (int32_t *)(w + L.queue[i]) : nullptr;
+        s1.gq[i] = L.present[i] ? w + L.gq[i] : nullptr;
+        if (L.present[i]) mask |= 1 << i;
+    }
+    s1.present_mask = mask;
+    if ((e = launch_stage1(s1, max_p, stream)) != hipSuccess) return hip_fail(e, "stage1");
+    prof.mark(0);
+    for (int i = 0; i < 4; ++i) {
+        if (!L.present[i]) continue;
+        const int pp = kPrimes[i];
+        if ((e = launch_plan(pp, (uint32_t *)(w + L.plan[i]), stream)) != hipSuccess) return hip_fail(e, "plan");
+        prof.mark(1);
+        DeepArgs da{};
+        da.mode = MODE_HEIGHT;
+        da.bound = bound;
+        da.heights = heights;
+        da.counters = counters;
+        da.queue = (const int32_t *)(w + L.queue[i]);
+        da.gq = w + L.gq[i];
+        da.plan = (const uint32_t *)(w + L.plan[i]);
+        da.slots = w + L.slots;
+        da.slot_bytes = L.slot_stride[i];
+        const int nslots = batch < L.nslots[i] ? batch : L.nslots[i];
+        if ((e = launch_deep(pp, da, nslots, stream)) != hipSuccess) return hip_fail(e, "deep");
+        prof.mark(2 + i);
+    }
+    return QFS_OK;
+}
+
+int qfs_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_prof.m);
+    g_prof.on = on != 0;
+    return QFS_OK;
+}
+
+int qfs_profile_collect(double ms[6], int *calls)
+{
+    if (!ms || !calls) return fail(QFS_EINVAL, "qfs_profile_collect: null pointer");
+    std::lock_guard<std::mutex> lk(g_prof.m);
+    for (int i = 0; i < 6; ++i) ms[i] = 0;
+    *calls = (int)g_prof.recs.size();
+    int rc = QFS_OK;
+    for (ProfRec &r : g_prof.recs) {
+        for (int i = 0; i < r.n; ++i)
+            if (hipEventSynchronize(r.ev[i]) != hipSuccess) rc = fail(QFS_EDEVICE, "qfs_profile_collect: event wait");
+        for (int i = 1; i < r.n; ++i) {
+            float t = 0;
+            if (r.stage[i] >= 0 && hipEventElapsedTime(&t, r.ev[i - 1], r.ev[i]) == hipSuccess) ms[r.stage[i]] += t;
+        }
+        for (int i = 0; i < r.n; ++i) g_prof.pool.push_back(r.ev[i]);
+    }
+    g_prof.recs.clear();
+    return rc;
+}
+
+int64_t qfs_mfma_per_surface(int p) { return supported(p) ? mfma_count(p) : -1; }
+
+// ---------------------------------------------------------------------------
+size_t qfs_height_plain_workspace_bytes(int p) { return supported(p) ? plain_scratch_bytes(p) : 0; }
+
+int qfs_height_plain(int p, int batch, const uint8_t *f, int bound, int32_t *heights, void *ws, size_t ws_bytes,
+                     hipStream_t stream)
+{
+    g_err[0] = 0;
+    if (!supported(p)) return fail(QFS_EUNSUPPORTED, "qfs_height_plain: p=%d not in {3,5,7,11}", p);
+    if (batch < 0) return fail(QFS_EINVAL, "qfs_height_plain: batch=%d < 0", batch);
+    if (bound < 1 || bound > 10) return fail(QFS_EINVAL, "qfs_height_plain: bound=%d outside 1..10", bound);
+    if (batch == 0) return QFS_OK;
+    if (!f || !heights || !ws) return fail(QFS_EINVAL, "qfs_height_plain: null pointer argument");
+    if (!aligned(ws)) return fail(QFS_EINVAL, "qfs_height_plain: workspace not 256-byte aligned");
+    const size_t need = plain_scratch_bytes(p);
+    if (ws_bytes < need) return fail(QFS_ENOMEM, "qfs_height_plain: workspace %zu bytes < %zu needed", ws_bytes, need);
+    for (int i = 0; i < batch; ++i) {
+        hipError_t e = launch_plain_surface(p, f + (size_t)i * 35, bound, heights + i, (uint8_t *)ws, stream);
+        if (e != hipSuccess) return hip_fail(e, "plain");
+    }
+    return QFS_OK;
+}
+
+}  // extern "C"

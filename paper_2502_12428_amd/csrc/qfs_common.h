@@ -1,0 +1,321 @@
+// Shared definitions for the libqfs HIP kernels (gfx950).
+//
+// Monomial index: a homogeneous form of degree n in x1..x4 is a byte array in
+// descending lexicographic order of (e1,e2,e3,e4).  The position of e is
+//     rank(e) = C(e2+e3+e4+2, 3) + C(e3+e4+1, 2) + e4,
+// which does not depend on n (it counts the tuples that precede e: those with
+// a larger e1, then a larger e2, then a larger e3).
+//
+// Dehomogenised coordinates drop x4 (the homogeneous form is determined by
+// its restriction x4 = 1 -- Section 5.1 of the paper uses the same fact for
+// its Kronecker substitution), so a form of degree n lives on the simplex
+// {x in Z^3 : x >= 0, x1+x2+x3 <= n}.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qfs {
+
+__host__ __device__ constexpr int64_t num_mono(int deg)
+{
+    return deg < 0 ? 0 : (int64_t)(deg + 3) * (deg + 2) * (deg + 1) / 6;
+}
+
+__host__ __device__ inline int64_t cns_rank(int e2, int e3, int e4)
+{
+    int64_t m1 = e2 + e3 + e4, m2 = e3 + e4;
+    return (m1 + 2) * (m1 + 1) * m1 / 6 + (m2 + 1) * m2 / 2 + e4;
+}
+
+// Inverse of cns_rank for degree n: exponents (e1,e2,e3,e4) of position r.
+__host__ __device__ inline void cns_unrank(int n, int64_t r, int &e1, int &e2, int &e3, int &e4)
+{
+    // m1 = e2+e3+e4 is the largest m with C(m+2,3) <= r
+    int m1 = (int)cbrtf((float)(6 * r + 1));
+    if (m1 > n) m1 = n;
+    while (m1 > 0 && (int64_t)(m1 + 2) * (m1 + 1) * m1 / 6 > r) --m1;
+    while (m1 < n && (int64_t)(m1 + 3) * (m1 + 2) * (m1 + 1) / 6 <= r) ++m1;
+    int64_t r1 = r - (int64_t)(m1 + 2) * (m1 + 1) * m1 / 6;
+    // m2 = e3+e4 is the largest m <= m1 with C(m+1,2) <= r1
+    int m2 = (int)sqrtf((float)(2 * r1 + 1));
+    if (m2 > m1) m2 = m1;
+    while (m2 > 0 && (int64_t)(m2 + 1) * m2 / 2 > r1) --m2;
+    while (m2 < m1 && (int64_t)(m2 + 2) * (m2 + 1) / 2 <= r1) ++m2;
+    e4 = (int)(r1 - (int64_t)(m2 + 1) * m2 / 2);
+    e3 = m2 - e4;
+    e2 = m1 - m2;
+    e1 = n - m1;
+}
+
+// The 35 exponent tuples of degree 4 in coefficient order, packed 8 bits each (e1..e4).
+struct B4Table {
+    uint32_t e[35];
+};
+__host__ __device__ constexpr B4Table make_b4()
+{
+    B4Table t{};
+    int i = 0;
+    for (int e1 = 4; e1 >= 0; --e1)
+        for (int e2 = 4 - e1; e2 >= 0; --e2)
+            for (int e3 = 4 - e1 - e2; e3 >= 0; --e3) {
+                int e4 = 4 - e1 - e2 - e3;
+                t.e[i++] = (uint32_t)e1 | ((uint32_t)e2 << 8) | ((uint32_t)e3 << 16) | ((uint32_t)e4 << 24);
+            }
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Per-prime sizes.
+// ---------------------------------------------------------------------------
+template <int P>
+struct Prime {
+    static constexpr int p = P;
+    static constexpr int p2 = P * P;
+    static constexpr int d = 4 * (P - 1);      // degree of g = f^(p-1)
+    static constexpr int D = P * d;            // degree of Delta_1(g)
+    static constexpr int len_g = (int)num_mono(d);
+    static constexpr int64_t len_D = num_mono(D);
+    // index of the monomial (x1 x2 x3 x4)^(p-1) in B_d
+    static constexpr int e_index = (int)((3 * (P - 1) + 2) * (3 * (P - 1) + 1) * (int64_t)(3 * (P - 1)) / 6 +
+                                         (2 * (P - 1) + 1) * (int64_t)(2 * (P - 1)) / 2 + (P - 1));
+};
+
+// ---------------------------------------------------------------------------
+// Block-Toeplitz geometry for the matrix-core product C = A * g (g of degree d).
+//
+// Dehomogenised positions are cut into tiles of T = (2,2,4) positions (16
+// bytes, position s = s1*8 + s2*4 + s3 inside the tile).  With output tile q
+// and input tile q - delta, the product restricted to one pair of tiles is a
+// 16x16 matrix W_delta[s][s'] = g[T*delta + s - s'] applied to the 16 input
+// bytes.  V is the set of offsets delta whose block can be nonzero for a
+// form of degree d: some T*delta + s - s' lies in {x >= 0, x1+x2+x3 <= d}.
+// ---------------------------------------------------------------------------
+constexpr int T1 = 2, T2 = 2, T3 = 4, TILE = 16;
+
+template <int P>
+struct Geo {
+    static constexpr int d = 4 * (P - 1);
+    static constexpr int D = P * d;
+    static constexpr bool valid(int a, int b, int c)
+    {
+        int s = 0;
+        if (a >= 1) s += T1 * (a - 1) + 1;
+        if (b >= 1) s += T2 * (b - 1) + 1;
+        if (c >= 1) s += T3 * (c - 1) + 1;
+        return s <= d;
+    }
+    static constexpr int H1 = (d - 1) / T1 + 1;   // largest delta coordinates
+    static constexpr int H2 = (d - 1) / T2 + 1;
+    static constexpr int H3 = (d - 1) / T3 + 1;
+    static constexpr int count()
+    {
+        int n = 0;
+        for (int a = 0; a <= H1; ++a)
+            for (int b = 0; b <= H2; ++b)
+                for (int c = 0; c <= H3; ++c)
+                    if (valid(a, b, c)) ++n;
+        return n;
+    }
+    static constexpr int NV = count();             // |V|
+    static constexpr int NQ = (NV + 3) / 4;        // quads of 4 offsets per MFMA K=64
+    static constexpr int NVP = NQ * 4;
+    // coarse tile box for degree D, with a halo of H below zero in each axis
+    static constexpr int C1 = D / T1 + 1, C2 = D / T2 + 1, C3 = D / T3 + 1;
+    static constexpr int B1 = H1 + C1, B2 = H2 + C2, B3 = H3 + C3;
+    static constexpr int64_t BOX_TILES = (int64_t)B1 * B2 * B3;
+    static constexpr int64_t BOX_BYTES = BOX_TILES * TILE;
+    static constexpr int64_t W_BYTES = (int64_t)NVP * 256;
+};
+
+// Offsets delta packed as 10-bit fields, sorted lexicographically, padded with
+// the zero offset (its W block is all zero).  Per quad: bounding box
+// (min and max per coordinate, packed) and the largest weight
+// w(delta) = 2 d1 + 2 d2 + 4 d3 over the quad.
+template <int P>
+struct DeltaTable {
+    uint32_t packed[Geo<P>::NVP];
+    int32_t toff[Geo<P>::NVP];        // tile-index offset in the padded box
+    uint32_t qmin[Geo<P>::NQ];
+    uint32_t qmax[Geo<P>::NQ];
+    int32_t qwmax[Geo<P>::NQ];
+};
+
+__host__ __device__ constexpr uint32_t pack3(int a, int b, int c)
+{
+    return (uint32_t)a | ((uint32_t)b << 10) | ((uint32_t)c << 20);
+}
+__host__ __device__ constexpr int unp0(uint32_t v) { return (int)(v & 1023u); }
+__host__ __device__ constexpr int unp1(uint32_t v) { return (int)((v >> 10) & 1023u); }
+__host__ __device__ constexpr int unp2(uint32_t v) { return (int)((v >> 20) & 1023u); }
+
+template <int P>
+constexpr DeltaTable<P> make_delta_table()
+{
+    using G = Geo<P>;
+    DeltaTable<P> t{};
+    int n = 0;
+    for (int a = 0; a <= G::H1; ++a)
+        for (int b = 0; b <= G::H2; ++b)
+            for (int c = 0; c <= G::H3; ++c)
+                if (G::valid(a, b, c)) {
+                    t.packed[n] = pack3(a, b, c);
+                    t.toff[n] = (a * G::B2 + b) * G::B3 + c;
+                    ++n;
+                }
+    for (; n < G::NVP; ++n) {
+        t.packed[n] = 0;
+        t.toff[n] = 0;
+    }
+    for (int q = 0; q < G::NQ; ++q) {
+        int lo[3] = {1 << 20, 1 << 20, 1 << 20}, hi[3] = {-1, -1, -1}, wmax = 0;
+        for (int i = 0; i < 4; ++i) {
+            uint32_t v = t.packed[4 * q + i];
+            int x[3] = {unp0(v), unp1(v), unp2(v)};
+            for (int j = 0; j < 3; ++j) {
+                if (x[j] < lo[j]) lo[j] = x[j];
+                if (x[j] > hi[j]) hi[j] = x[j];
+            }
+            int w = T1 * x[0] + T2 * x[1] + T3 * x[2];
+            if (w > wmax) wmax = w;
+        }
+        t.qmin[q] = pack3(lo[0], lo[1], lo[2]);
+        t.qmax[q] = pack3(hi[0], hi[1], hi[2]);
+        t.qwmax[q] = wmax;
+    }
+    return t;
+}
+
+// Number of output tiles with w(c) = 2 c1 + 2 c2 + 4 c3 <= n, c >= 0.
+__host__ __device__ constexpr int64_t tiles_upto(int n)
+{
+    if (n < 0) return 0;
+    int64_t cnt = 0;
+    for (int a = 0; T1 * a <= n; ++a)
+        for (int b = 0; T1 * a + T2 * b <= n; ++b)
+            cnt += (n - T1 * a - T2 * b) / T3 + 1;
+    return cnt;
+}
+
+}  // namespace qfs
+
+namespace qfs {
+
+// ---------------------------------------------------------------------------
+// Cartier-split layout of Delta for the map theta(a)[r] = sum_c Delta[p r + e - c] a[c]
+// (e = (p-1,...,p-1)).  Writing c = p c' + s with s = c mod p gives
+// p r + e - c = p (r - c') + (e - s): the Delta coefficient sits in residue
+// class sigma = e - s at "coarse" position y = r - c'.  Only pairs whose
+// exponents add to e mod p survive u (Section 4, Corollary "unique match"),
+// and for c of degree d = 4(p-1) the coarse part c' has degree j <= d/p < 4.
+//
+// Delta is stored per j (the degree of c'): region j is a row-major matrix
+// with one row per y in B_{d-j} (CNS order) and one column per s in S_j =
+// {s in [0,p)^4 : |s| = d - p j} (lexicographic s, row stride padded to 16).
+// theta then reads, for each output r and each c' <= r, one contiguous row.
+// ---------------------------------------------------------------------------
+template <int P>
+struct ThetaGeo {
+    static constexpr int d = 4 * (P - 1);
+    static constexpr int D = P * d;
+    static constexpr int J = d / P + 1;  // j = 0..J-1
+    static constexpr int ns(int j)
+    {
+        int n = 0, target = d - P * j;
+        for (int a = 0; a < P; ++a)
+            for (int b = 0; b < P; ++b)
+                for (int c = 0; c < P; ++c) {
+                    int e = target - a - b - c;
+                    if (e >= 0 && e < P) ++n;
+                }
+        return n;
+    }
+    static constexpr int rs(int j) { return (ns(j) + 15) / 16 * 16; }
+    static constexpr int64_t region_off(int j)
+    {
+        int64_t o = 0;
+        for (int i = 0; i < j; ++i) o += num_mono(d - i) * rs(i);
+        return o;
+    }
+    static constexpr int64_t BYTES = region_off(J);
+    static constexpr int count_cp()
+    {
+        int n = 0;
+        for (int j = 0; j < J; ++j) n += (int)num_mono(j);
+        return n;
+    }
+    static constexpr int count_aperm()
+    {
+        int n = 0;
+        for (int j = 0; j < J; ++j) n += (int)num_mono(j) * rs(j);
+        return n;
+    }
+    static constexpr int NCP = count_cp();       // number of coarse parts c' (35 when J = 4)
+    static constexpr int APERM = count_aperm();  // bytes of the permuted input vector
+    static constexpr int NSIG = P * P * P * P;
+};
+
+template <int P>
+struct ThetaTable {
+    int16_t sidx[ThetaGeo<P>::NSIG];        // sigma code -> column in its region, -1 if |sigma| != 0 mod p
+    uint16_t aperm_src[ThetaGeo<P>::APERM]; // a_perm slot -> position in B_d, 0xFFFF = padding
+    uint32_t cprime[ThetaGeo<P>::NCP];      // c' exponents packed 8 bits each
+    int32_t cp_seg[ThetaGeo<P>::NCP];       // start of c''s segment in a_perm
+    int32_t cp_j[ThetaGeo<P>::NCP];
+    int32_t rs[4];
+    int64_t roff[4];
+};
+
+template <int P>
+constexpr ThetaTable<P> make_theta_table()
+{
+    using TG = ThetaGeo<P>;
+    ThetaTable<P> t{};
+    constexpr int d = TG::d;
+    for (int i = 0; i < TG::NSIG; ++i) t.sidx[i] = -1;
+    for (int j = 0; j < 4; ++j) {
+        t.rs[j] = j < TG::J ? TG::rs(j) : 0;
+        t.roff[j] = j < TG::J ? TG::region_off(j) : TG::BYTES;
+    }
+    int seg = 0, ncp = 0;
+    for (int j = 0; j < TG::J; ++j) {
+        // S_j in lexicographic order; sidx of sigma = e - s
+        int s_list_n = 0;
+        int target = d - P * j;
+        for (int a = 0; a < P; ++a)
+            for (int b = 0; b < P; ++b)
+                for (int c = 0; c < P; ++c) {
+                    int e = target - a - b - c;
+                    if (e < 0 || e >= P) continue;
+                    int sg = (((P - 1 - a) * P + (P - 1 - b)) * P + (P - 1 - c)) * P + (P - 1 - e);
+                    t.sidx[sg] = (int16_t)s_list_n++;
+                }
+        // c' in B_j (descending lex) and their a_perm segments
+        for (int c1 = j; c1 >= 0; --c1)
+            for (int c2 = j - c1; c2 >= 0; --c2)
+                for (int c3 = j - c1 - c2; c3 >= 0; --c3) {
+                    int c4 = j - c1 - c2 - c3;
+                    t.cprime[ncp] = (uint32_t)c1 | ((uint32_t)c2 << 8) | ((uint32_t)c3 << 16) | ((uint32_t)c4 << 24);
+                    t.cp_seg[ncp] = seg;
+                    t.cp_j[ncp] = j;
+                    int k = 0;
+                    for (int a = 0; a < P; ++a)
+                        for (int b = 0; b < P; ++b)
+                            for (int c = 0; c < P; ++c) {
+                                int e = target - a - b - c;
+                                if (e < 0 || e >= P) continue;
+                                int x2 = P * c2 + b, x3 = P * c3 + c, x4 = P * c4 + e;
+                                int64_t m1 = x2 + x3 + x4, m2 = x3 + x4;
+                                t.aperm_src[seg + k] =
+                                    (uint16_t)((m1 + 2) * (m1 + 1) * m1 / 6 + (m2 + 1) * m2 / 2 + x4);
+                                ++k;
+                            }
+                    for (; k < TG::rs(j); ++k) t.aperm_src[seg + k] = 0xFFFF;
+                    seg += TG::rs(j);
+                    ++ncp;
+                }
+    }
+    return t;
+}
+
+}  // namespace qfs

@@ -11,6 +11,7 @@
 //   fused into the last product (Algorithm 1, lines 3-5), then the theta loop
 //   of Algorithm 3 with its one-coefficient test.
 #include <algorithm>
+#include <cstdlib>
 #include <vector>
 
 #include "qfs_device.h"
@@ -125,37 +126,49 @@ hipError_t launch_stage1(const Stage1Args &a, int max_p, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// plan: output tile lists
+// plan: output tile lists (base tiles of the super-tiles, and shell lists)
 // ---------------------------------------------------------------------------
 template <int P>
 __global__ __launch_bounds__(256) void k_plan(uint32_t *plan)
 {
+    using X = GeoX<P>;
     constexpr int d = 4 * (P - 1);
-    const int k = blockIdx.x;
-    const int n = (k + 1) * d;
-    uint32_t *out = plan + kPT<P>.off[k];
+    const bool is_base = blockIdx.x < P;
+    const int k = is_base ? blockIdx.x : blockIdx.x - P;
+    if (is_base ? (k < 1) : (k > P - 2)) return;
+    const int m = is_base ? (k + 1) * d : (k + 2) * d + 4;
+    uint32_t *out = plan + (is_base ? kPT<P>.boff[k] : kPT<P>.foff[k]);
     __shared__ int cnt[256];
     const int c1 = threadIdx.x;
+    const int step = is_base ? 2 : 1;
+    const bool mine_slab = (c1 % step == 0) && T1 * c1 <= m && (is_base || c1 <= X::C1);
     int mine = 0;
-    if (T1 * c1 <= n)
-        for (int c2 = 0; T1 * c1 + T2 * c2 <= n; ++c2) mine += (n - T1 * c1 - T2 * c2) / T3 + 1;
+    if (mine_slab)
+        for (int c2 = 0; T1 * c1 + T2 * c2 <= m && (is_base || c2 <= X::C2); c2 += step) {
+            int top = (m - T1 * c1 - T2 * c2) / T3;
+            if (!is_base && top > X::C3 - 1) top = X::C3 - 1;
+            mine += top + 1;
+        }
     cnt[c1] = mine;
     __syncthreads();
-    if (T1 * c1 <= n) {
+    if (mine_slab) {
         int off = 0;
         for (int i = 0; i < c1; ++i) off += cnt[i];
-        for (int c2 = 0; T1 * c1 + T2 * c2 <= n; ++c2)
-            for (int c3 = 0; T1 * c1 + T2 * c2 + T3 * c3 <= n; ++c3) out[off++] = pack3(c1, c2, c3);
+        for (int c2 = 0; T1 * c1 + T2 * c2 <= m && (is_base || c2 <= X::C2); c2 += step) {
+            int top = (m - T1 * c1 - T2 * c2) / T3;
+            if (!is_base && top > X::C3 - 1) top = X::C3 - 1;
+            for (int c3 = 0; c3 <= top; ++c3) out[off++] = pack3(c1, c2, c3);
+        }
     }
 }
 
 hipError_t launch_plan(int p, uint32_t *plan, hipStream_t s)
 {
     switch (p) {
-    case 3: hipLaunchKernelGGL(k_plan<3>, dim3(3), dim3(256), 0, s, plan); break;
-    case 5: hipLaunchKernelGGL(k_plan<5>, dim3(5), dim3(256), 0, s, plan); break;
-    case 7: hipLaunchKernelGGL(k_plan<7>, dim3(7), dim3(256), 0, s, plan); break;
-    case 11: hipLaunchKernelGGL(k_plan<11>, dim3(11), dim3(256), 0, s, plan); break;
+    case 3: hipLaunchKernelGGL(k_plan<3>, dim3(6), dim3(256), 0, s, plan); break;
+    case 5: hipLaunchKernelGGL(k_plan<5>, dim3(10), dim3(256), 0, s, plan); break;
+    case 7: hipLaunchKernelGGL(k_plan<7>, dim3(14), dim3(256), 0, s, plan); break;
+    case 11: hipLaunchKernelGGL(k_plan<11>, dim3(22), dim3(256), 0, s, plan); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -167,50 +180,58 @@ hipError_t launch_plan(int p, uint32_t *plan, hipStream_t s)
 constexpr int DEEP_NT = 512, DEEP_NW = DEEP_NT / 64, DEEP_NB = 4;
 
 template <int P>
+__constant__ DeltaTableX<P> kDX = make_delta_table_x<P>();
+
+template <int P>
 struct DeepLds {
+    using X = GeoX<P>;
     static constexpr int LG = Prime<P>::len_g;
     static constexpr int LGA = (LG + 15) / 16 * 16;
     static constexpr int APA = (ThetaGeo<P>::APERM + 15) / 16 * 16;
-    static constexpr int off_g = 0;
+    static constexpr int WB = w_in_lds<P>() ? (int)((X::W_BYTES + 15) / 16 * 16) : 0;
+    static constexpr int off_w = 0;
+    static constexpr int off_g = off_w + WB;
     static constexpr int off_aperm = off_g + LGA;
     static constexpr int off_toff = off_aperm + APA;
-    static constexpr int off_red = off_toff + 4 * Geo<P>::NVP;
-    static constexpr int bytes = off_red + 4 * 32;
+    static constexpr int off_widx = off_toff + 4 * X::NVXP;
+    static constexpr int off_red = off_widx + 8 * X::NVXP;
+    static constexpr int bytes = off_red + 4 * 64;
 };
 
 template <int P>
 __device__ inline int64_t box_tile(int c1, int c2, int c3)
 {
-    using G = Geo<P>;
-    return ((int64_t)(c1 + G::H1) * G::B2 + (c2 + G::H2)) * G::B3 + (c3 + G::H3);
+    using X = GeoX<P>;
+    return ((int64_t)(c1 + X::H1) * X::B2 + (c2 + X::H2)) * X::B3 + (c3 + X::H3);
 }
 
-// Fill W[delta][s][s'] = g~[T*delta + s - s'] (dehomogenised, zero outside the simplex of degree d).
+// W[v][s][s'] = g~[T*v + s - s'] for v in V (dehomogenised, zero outside the
+// simplex of degree d); block NV is all zero.
 template <int P>
 __device__ void build_w(const uint8_t *g, uint8_t *W)
 {
-    using G = Geo<P>;
-    constexpr int d = G::d;
-    for (int row = threadIdx.x; row < G::NVP * 16; row += blockDim.x) {
-        const int q = row >> 4, s = row & 15;
+    using X = GeoX<P>;
+    constexpr int d = X::d;
+    for (int row = threadIdx.x; row < (X::NV + 1) * 16; row += blockDim.x) {
+        const int v = row >> 4, s = row & 15;
         const int s1 = s >> 3, s2 = (s >> 2) & 1, s3 = s & 3;
         unsigned w[4] = {0, 0, 0, 0};
-        if (q < G::NV) {
-            const uint32_t dl = kDT<P>.packed[q];
+        if (v < X::NV) {
+            const uint32_t dl = kDX<P>.vpacked[v];
             const int b1 = T1 * unp0(dl) + s1, b2 = T2 * unp1(dl) + s2, b3 = T3 * unp2(dl) + s3;
             for (int sp = 0; sp < 16; ++sp) {
                 const int x1 = b1 - (sp >> 3), x2 = b2 - ((sp >> 2) & 1), x3 = b3 - (sp & 3);
                 const int x4 = d - x1 - x2 - x3;
-                unsigned v = 0;
-                if (x1 >= 0 && x2 >= 0 && x3 >= 0 && x4 >= 0) v = g[cns_rank(x2, x3, x4)];
-                w[sp >> 2] |= v << (8 * (sp & 3));
+                unsigned val = 0;
+                if (x1 >= 0 && x2 >= 0 && x3 >= 0 && x4 >= 0) val = g[cns_rank(x2, x3, x4)];
+                w[sp >> 2] |= val << (8 * (sp & 3));
             }
         }
         *(v4u *)(W + (size_t)row * 16) = v4u{w[0], w[1], w[2], w[3]};
     }
 }
 
-// A_1 = g~ on the tiles with w(c) <= 2d (zero beyond degree d).
+// A_1 = g~ on the shell list 0 (every tile with w(c) <= 2d + 4; zero beyond degree d).
 template <int P>
 __device__ void init_a1(const uint8_t *g, const uint32_t *list, int ntiles, uint8_t *A)
 {
@@ -226,25 +247,19 @@ __device__ void init_a1(const uint8_t *g, const uint32_t *list, int ntiles, uint
                 if (x4 >= 0) w[s >> 2] |= (unsigned)g[cns_rank(x2, x3, x4)] << (8 * (s & 3));
             }
         }
-        *(v4u *)(A + box_tile<P>(c1, c2, c3) * 16) = v4u{w[0], w[1], w[2], w[3]};
+        gstore16(A + box_tile<P>(c1, c2, c3) * 16, v4u{w[0], w[1], w[2], w[3]});
     }
 }
 
-// Zero the tiles of `list` with w(c) > n (the shell the next product reads beyond degree n).
+// Zero the tiles of a shell list with w(c) > n: the next product reads them as zeros.
 template <int P>
 __device__ void zero_shell(const uint32_t *list, int ntiles, int n, uint8_t *A)
 {
     for (int i = threadIdx.x; i < ntiles; i += blockDim.x) {
         const uint32_t t = list[i];
         const int c1 = unp0(t), c2 = unp1(t), c3 = unp2(t);
-        if (T1 * c1 + T2 * c2 + T3 * c3 > n) *(v4u *)(A + box_tile<P>(c1, c2, c3) * 16) = v4u{0, 0, 0, 0};
+        if (T1 * c1 + T2 * c2 + T3 * c3 > n) gstore16(A + box_tile<P>(c1, c2, c3) * 16, v4u{0, 0, 0, 0});
     }
-}
-
-template <int P>
-__device__ inline int ntiles_of_list(int k)
-{
-    return (int)kPT<P>.len[k];
 }
 
 struct EpiCtx {
@@ -255,17 +270,47 @@ struct EpiCtx {
     int *err;         // LDS flag
 };
 
-// One wave computes NB groups of 16 output tiles of A_{k+1} = A_k * g~:
-// for each quad of 4 offsets, D[s][tile] += W_quad[s][(delta,s')] * A_tile[(delta,s')].
+// Delta_1 epilogue for the four positions s = 4 kg + v of output tile c:
+// D = (g~^p - sum_J b_J^p x^(pJ)) / p mod p (Algorithm 1, lines 3-5).
 template <int P>
-__device__ void mfma_set(const uint32_t *list, int ntiles, int gs, int nk, const uint8_t *__restrict__ W,
-                         const uint8_t *__restrict__ Ain, uint8_t *Aout, bool last, const int *toff_l,
-                         const EpiCtx &ec)
+__device__ __attribute__((always_inline)) inline void epilogue(int c1, int c2, int c3, int kg, v4i acc,
+                                                               const EpiCtx &ec)
 {
-    using G = Geo<P>;
+    constexpr int P2 = P * P, D = 4 * P * (P - 1);
+    const int x1 = T1 * c1 + (kg >> 1), x2 = T2 * c2 + (kg & 1);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int x3 = T3 * c3 + v;
+        const int x4 = D - x1 - x2 - x3;
+        if (x4 < 0) continue;
+        int val = acc[v] % P2;
+        if (x1 % P == 0 && x2 % P == 0 && x3 % P == 0) {
+            const int bj = ec.g[cns_rank(x2 / P, x3 / P, x4 / P)];
+            val -= pow_p_mod_p2<P>(bj);
+            if (val < 0) val += P2;
+        }
+        if (val % P) *ec.err = 1;
+        const uint8_t dv = (uint8_t)(val / P);
+        if (ec.mode == MODE_HEIGHT)
+            gstore1(ec.dl + theta_addr<P>(x1, x2, x3, x4), dv);
+        else
+            gstore1(ec.dout + cns_rank(x2, x3, x4), dv);
+    }
+}
+
+// One wave computes NB groups of 16 base tiles and their four shifts, i.e.
+// 4 * NB output groups of A_{k+1} = A_k * g~.  Per quad of offsets delta it
+// loads one input fragment per group (the 16 tiles q - delta) and one W
+// fragment per shift (blocks W_{delta + Delta_s}), then issues up to
+// 4 * NB products D[s][tile] += W[s][(delta, s')] * A[(delta, s')][tile].
+template <int P>
+__device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *list, int nbase, int gs, int nk, const uint8_t *W,
+                         const uint8_t *__restrict__ Ain, uint8_t *Aout, bool last, const int *toff_l,
+                         const uint32_t *widx_l, const EpiCtx &ec)
+{
+    using X = GeoX<P>;
     constexpr int NB = DEEP_NB;
     constexpr int P2 = P * P;
-    constexpr int D = G::D;
     const int lane = threadIdx.x & 63, kg = lane >> 4, col = lane & 15;
 
     int64_t base[NB];
@@ -275,9 +320,9 @@ __device__ void mfma_set(const uint32_t *list, int ntiles, int gs, int nk, const
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int g0 = (gs * NB + b) * 16;
-        gex[b] = g0 < ntiles;
+        gex[b] = g0 < nbase;
         const int idx = g0 + col;
-        ok[b] = idx < ntiles;
+        ok[b] = idx < nbase;
         const uint32_t t = gex[b] ? list[ok[b] ? idx : g0] : 0u;
         tpk[b] = t;
         const int c1 = unp0(t), c2 = unp1(t), c3 = unp2(t);
@@ -287,62 +332,82 @@ __device__ void mfma_set(const uint32_t *list, int ntiles, int gs, int nk, const
         gmax3[b] = uniform(wave_max(c3));
         gwmin[b] = uniform(wave_min(T1 * c1 + T2 * c2 + T3 * c3));
     }
-    v4i acc[NB];
+    v4i acc[4][NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = v4i{0, 0, 0, 0};
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[s][b] = v4i{0, 0, 0, 0};
 
-    for (int q = 0; q < G::NQ; ++q) {
-        const uint32_t qmin = kDT<P>.qmin[q];
-        const int qw = kDT<P>.qwmax[q];
-        const int qm1 = unp0(qmin), qm2 = unp1(qmin), qm3 = unp2(qmin);
-        bool need[NB];
-        bool any = false;
+    // bit b set: the input tiles of group b for quad q can be nonzero (scalar bounding-box test)
+    auto need_mask = [&](int q) -> uint32_t {
+        const uint32_t qmin = kDX<P>.qmin[q];
+        const int qw = kDX<P>.qwmax[q];
+        const int qm1 = unp0(qmin) - 1, qm2 = unp1(qmin) - 1, qm3 = unp2(qmin);
+        uint32_t m = 0;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            need[b] = gex[b] && gmax1[b] >= qm1 && gmax2[b] >= qm2 && gmax3[b] >= qm3 && gwmin[b] - qw <= nk;
-            any |= need[b];
-        }
-        if (!any) continue;
-        const v4i wf = *(const v4i *)(W + (size_t)q * 1024 + lane * 16);
+        for (int b = 0; b < NB; ++b)
+            if (gex[b] && gmax1[b] >= qm1 && gmax2[b] >= qm2 && gmax3[b] >= qm3 && gwmin[b] - qw <= nk) m |= 1u << b;
+        return (uint32_t)uniform((int)m);
+    };
+
+    v4i bf[NB], bfn[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) bf[b] = bfn[b] = v4i{0, 0, 0, 0};
+    int q = 0;
+    uint32_t need = 0;
+    while (q < X::NQX && !(need = need_mask(q))) ++q;
+    // every group's fragment is loaded (its address is inside the box even when the group
+    // is absent or skipped), so the number of loads in flight is fixed per iteration
+    if (q < X::NQX) {
         const int to = toff_l[4 * q + kg];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            if (!need[b]) continue;
-            const v4i bf = *(const v4i *)(Ain + (base[b] - to) * 16);
-            acc[b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(wf, bf, acc[b], 0, 0, 0);
+        for (int b = 0; b < NB; ++b) bf[b] = gload16(Ain + (base[b] - to) * 16);
+    }
+    while (q < X::NQX) {
+        // issue the next needed quad's input loads before this quad's products
+        int qn = q + 1;
+        uint32_t need_n = 0;
+        while (qn < X::NQX && !(need_n = need_mask(qn))) ++qn;
+        {
+            // issued on every iteration (the last one reloads quad q) so that the wait
+            // before this quad's products is the same on every path
+            const int to = toff_l[4 * (qn < X::NQX ? qn : q) + kg];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) bfn[b] = gload16(Ain + (base[b] - to) * 16);
         }
+        const uint32_t nz = kDX<P>.wnz[q];
+        const uint32_t w01 = widx_l[2 * (4 * q + kg)], w23 = widx_l[2 * (4 * q + kg) + 1];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (!((nz >> s) & 1)) continue;
+            const uint32_t wi = ((s < 2 ? w01 : w23) >> (16 * (s & 1))) & 0xFFFFu;
+            const v4i wf = w_in_lds<P>() ? *(const v4i *)(W + wi * 256 + col * 16) : gload16(W + wi * 256 + col * 16);
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                if ((need >> b) & 1) acc[s][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(wf, bf[b], acc[s][b], 0, 0, 0);
+        }
+        q = qn;
+        need = need_n;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) bf[b] = bfn[b];
     }
 
+    constexpr int64_t SH1 = (int64_t)X::B2 * X::B3, SH2 = X::B3;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         if (!gex[b] || !ok[b]) continue;
-        if (!last) {
-            unsigned packed = 0;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) packed |= (unsigned)(acc[b][v] % P2) << (8 * v);
-            *(unsigned *)(Aout + base[b] * 16 + 4 * kg) = packed;
-            continue;
-        }
-        // Delta_1 epilogue: D = (g~^p - sum_J b_J^p x^(pJ)) / p mod p
         const int c1 = unp0(tpk[b]), c2 = unp1(tpk[b]), c3 = unp2(tpk[b]);
-        const int x1 = T1 * c1 + (kg >> 1), x2 = T2 * c2 + (kg & 1);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int x3 = T3 * c3 + v;
-            const int x4 = D - x1 - x2 - x3;
-            if (x4 < 0) continue;
-            int val = acc[b][v] % P2;
-            if (x1 % P == 0 && x2 % P == 0 && x3 % P == 0) {
-                const int bj = ec.g[cns_rank(x2 / P, x3 / P, x4 / P)];
-                val -= pow_p_mod_p2<P>(bj);
-                if (val < 0) val += P2;
+        for (int s = 0; s < 4; ++s) {
+            const int d1 = s & 1, d2 = s >> 1;
+            if (!last) {
+                unsigned packed = 0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) packed |= (unsigned)(acc[s][b][v] % P2) << (8 * v);
+                gstore4(Aout + (base[b] + d1 * SH1 + d2 * SH2) * 16 + 4 * kg, packed);
+            } else {
+                epilogue<P>(c1 + d1, c2 + d2, c3, kg, acc[s][b], ec);
             }
-            if (val % P) *ec.err = 1;
-            const uint8_t dv = (uint8_t)(val / P);
-            if (ec.mode == MODE_HEIGHT)
-                ec.dl[theta_addr<P>(x1, x2, x3, x4)] = dv;
-            else
-                ec.dout[cns_rank(x2, x3, x4)] = dv;
         }
     }
 }
@@ -351,7 +416,7 @@ template <int P>
 __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
 {
     using PR = Prime<P>;
-    using G = Geo<P>;
+    using X = GeoX<P>;
     using L = DeepLds<P>;
     constexpr int LG = PR::len_g;
     constexpr int d = PR::d;
@@ -359,28 +424,36 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
     uint8_t *g_l = lds + L::off_g;
     uint8_t *aperm = lds + L::off_aperm;
     int *toff_l = (int *)(lds + L::off_toff);
+    uint32_t *widx_l = (uint32_t *)(lds + L::off_widx);
     int *red = (int *)(lds + L::off_red);
     __shared__ int s_pos, s_err;
 
-    const int tid = threadIdx.x, wave = tid >> 6;
+    const int tid = threadIdx.x, wave = uniform(tid >> 6);
     const int pi = prime_index(P);
     uint8_t *slot = a.slots + (size_t)blockIdx.x * a.slot_bytes;
-    uint8_t *W = slot;
-    uint8_t *buf[2] = {slot + align256(G::W_BYTES), slot + align256(G::W_BYTES) + align256(G::BOX_BYTES)};
-    uint8_t *dl = slot + align256(G::W_BYTES) + 2 * align256(G::BOX_BYTES);
+    uint8_t *wg = slot;
+    uint8_t *bufs = slot + (w_in_lds<P>() ? 0 : align256(X::W_BYTES));
+    uint8_t *buf[2] = {bufs, bufs + align256(X::BOX_BYTES)};
+    uint8_t *dl = bufs + 2 * align256(X::BOX_BYTES);
+    uint8_t *W = w_in_lds<P>() ? lds + L::off_w : wg;
 
-    for (int i = tid; i < G::NVP; i += DEEP_NT) toff_l[i] = kDT<P>.toff[i];
+    const int count = a.counters[CNT_COUNT + pi];
+    if ((int)blockIdx.x >= count) return;  // more workgroups than surfaces: nothing to do
+    for (int i = tid; i < X::NVXP; i += DEEP_NT) {
+        toff_l[i] = kDX<P>.toff[i];
+        widx_l[2 * i] = kDX<P>.widx[i][0];
+        widx_l[2 * i + 1] = kDX<P>.widx[i][1];
+    }
     // the halo (tiles with a negative coordinate) of both boxes is read as zero and never written
-    for (int64_t t = tid; t < G::BOX_TILES; t += DEEP_NT) {
-        const int i3 = (int)(t % G::B3);
-        const int64_t r = t / G::B3;
-        const int i2 = (int)(r % G::B2), i1 = (int)(r / G::B2);
-        if (i1 < G::H1 || i2 < G::H2 || i3 < G::H3) {
-            *(v4u *)(buf[0] + t * 16) = v4u{0, 0, 0, 0};
-            *(v4u *)(buf[1] + t * 16) = v4u{0, 0, 0, 0};
+    for (int64_t t = tid; t < X::BOX_TILES; t += DEEP_NT) {
+        const int i3 = (int)(t % X::B3);
+        const int64_t r = t / X::B3;
+        const int i2 = (int)(r % X::B2), i1 = (int)(r / X::B2);
+        if (i1 < X::H1 || i2 < X::H2 || i3 < X::H3) {
+            gstore16(buf[0] + t * 16, v4u{0, 0, 0, 0});
+            gstore16(buf[1] + t * 16, v4u{0, 0, 0, 0});
         }
     }
-    const int count = a.counters[CNT_COUNT + pi];
 
     for (;;) {
         __syncthreads();
@@ -395,7 +468,7 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
         for (int i = tid; i < LG; i += DEEP_NT) g_l[i] = a.gq[(size_t)pos * LG + i];
         __syncthreads();
         build_w<P>(g_l, W);
-        init_a1<P>(g_l, a.plan + kPT<P>.off[1], ntiles_of_list<P>(1), buf[0]);
+        init_a1<P>(g_l, a.plan + kPT<P>.foff[0], (int)kPT<P>.flen[0], buf[0]);
         __syncthreads();
 
         EpiCtx ec;
@@ -407,13 +480,13 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
         for (int k = 1; k < P; ++k) {
             const uint8_t *Ain = buf[(k - 1) & 1];
             uint8_t *Aout = buf[k & 1];
-            const int ntiles = ntiles_of_list<P>(k);
-            const int nsets = ((ntiles + 15) / 16 + DEEP_NB - 1) / DEEP_NB;
+            const int nbase = (int)kPT<P>.blen[k];
+            const int nsets = ((nbase + 15) / 16 + DEEP_NB - 1) / DEEP_NB;
             const bool last = (k == P - 1);
-            const uint32_t *list = a.plan + kPT<P>.off[k];
+            const uint32_t *list = a.plan + kPT<P>.boff[k];
             for (int gs = wave; gs < nsets; gs += DEEP_NW)
-                mfma_set<P>(list, ntiles, gs, k * d, W, Ain, Aout, last, toff_l, ec);
-            if (!last) zero_shell<P>(a.plan + kPT<P>.off[k + 1], ntiles_of_list<P>(k + 1), (k + 1) * d, Aout);
+                mfma_set<P>(list, nbase, gs, k * d, W, Ain, Aout, last, toff_l, widx_l, ec);
+            if (!last) zero_shell<P>(a.plan + kPT<P>.foff[k], (int)kPT<P>.flen[k], (k + 1) * d, Aout);
             __syncthreads();
         }
         const bool err = s_err != 0;
@@ -449,6 +522,9 @@ template <int P>
 static hipError_t launch_deep_p(const DeepArgs &a, int nslots, hipStream_t s)
 {
     const size_t lds = DeepLds<P>::bytes;
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void *)k_deep<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL(k_deep<P>, dim3(nslots), dim3(DEEP_NT), lds, s, a);
     return hipGetLastError();
 }
@@ -465,21 +541,21 @@ hipError_t launch_deep(int p, const DeepArgs &a, int nslots, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// MFMA instructions per surface (host): the deep kernel's skip test depends
-// only on the geometry, so this replays it.
+// MFMA instructions per surface (host): the deep kernel's skip tests depend
+// only on the geometry, so this replays them.
 // ---------------------------------------------------------------------------
 template <int P>
 static int64_t mfma_count_p()
 {
-    using G = Geo<P>;
-    constexpr int d = G::d;
-    static const DeltaTable<P> DT = make_delta_table<P>();
+    using X = GeoX<P>;
+    constexpr int d = X::d;
+    static const DeltaTableX<P> DX = make_delta_table_x<P>();
     int64_t total = 0;
     for (int k = 1; k < P; ++k) {
         const int n = (k + 1) * d, nk = k * d;
         std::vector<uint32_t> tiles;
-        for (int c1 = 0; T1 * c1 <= n; ++c1)
-            for (int c2 = 0; T1 * c1 + T2 * c2 <= n; ++c2)
+        for (int c1 = 0; T1 * c1 <= n; c1 += 2)
+            for (int c2 = 0; T1 * c1 + T2 * c2 <= n; c2 += 2)
                 for (int c3 = 0; T1 * c1 + T2 * c2 + T3 * c3 <= n; ++c3) tiles.push_back(pack3(c1, c2, c3));
         const int nt = (int)tiles.size();
         for (int g0 = 0; g0 < nt; g0 += 16) {
@@ -491,9 +567,10 @@ static int64_t mfma_count_p()
                 m3 = std::max(m3, unp2(t));
                 wmin = std::min(wmin, T1 * unp0(t) + T2 * unp1(t) + T3 * unp2(t));
             }
-            for (int q = 0; q < G::NQ; ++q) {
-                const uint32_t qm = DT.qmin[q];
-                if (m1 >= unp0(qm) && m2 >= unp1(qm) && m3 >= unp2(qm) && wmin - DT.qwmax[q] <= nk) ++total;
+            for (int q = 0; q < X::NQX; ++q) {
+                const uint32_t qm = DX.qmin[q];
+                if (m1 >= unp0(qm) - 1 && m2 >= unp1(qm) - 1 && m3 >= unp2(qm) && wmin - DX.qwmax[q] <= nk)
+                    total += __builtin_popcount(DX.wnz[q]);
             }
         }
     }
@@ -546,6 +623,14 @@ static size_t plan_bytes_of(int p)
     return 0;
 }
 
+// Persistent workgroups per compute unit for p <= 7 (QFS_DEEP_WGS_PER_CU, 1..8; default 1).
+static int deep_wgs_per_cu()
+{
+    const char *e = getenv("QFS_DEEP_WGS_PER_CU");
+    int v = e ? atoi(e) : 1;
+    return v < 1 ? 1 : v > 8 ? 8 : v;
+}
+
 BatchLayout make_batch_layout(const bool present[4], int batch, int n_cu)
 {
     BatchLayout L;
@@ -561,7 +646,7 @@ BatchLayout make_batch_layout(const bool present[4], int batch, int n_cu)
         L.plan[i] = off;
         off += align256(plan_bytes_of(p));
         // one persistent workgroup per compute unit; p = 11 boxes are large, so fewer
-        int ns = p == 11 ? (n_cu < 64 ? n_cu : 64) : n_cu;
+        int ns = p == 11 ? (n_cu < 64 ? n_cu : 64) : n_cu * deep_wgs_per_cu();
         if (ns > batch) ns = batch;
         L.nslots[i] = ns > 0 ? ns : 1;
         L.slot_stride[i] = slot_bytes_of(p);

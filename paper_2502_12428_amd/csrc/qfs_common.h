@@ -186,6 +186,123 @@ constexpr DeltaTable<P> make_delta_table()
     return t;
 }
 
+// ---------------------------------------------------------------------------
+// Super-tile form of the product used by the deep kernel.  Output tiles are
+// grouped in 2x2 super-tiles in (c1, c2): a base tile q (c1, c2 even) and its
+// shifts q + Delta_s, Delta in {0, e1, e2, e1+e2}.  For an input tile q - delta
+// the four outputs q + Delta_s use the blocks W_{delta + Delta_s}, so one
+// loaded input fragment feeds four matrix-core products.  The offsets delta
+// run over VX = union over s of (V - Delta_s) (components >= -1 in c1, c2).
+// ---------------------------------------------------------------------------
+template <int P>
+struct GeoX {
+    using G = Geo<P>;
+    static constexpr int d = G::d, D = G::D, NV = G::NV;
+    static constexpr int H1 = G::H1, H2 = G::H2, H3 = G::H3;
+    static constexpr bool inV(int a, int b, int c)
+    {
+        return a >= 0 && b >= 0 && c >= 0 && a <= H1 && b <= H2 && c <= H3 && G::valid(a, b, c);
+    }
+    static constexpr bool inVX(int a, int b, int c)
+    {
+        return inV(a, b, c) || inV(a + 1, b, c) || inV(a, b + 1, c) || inV(a + 1, b + 1, c);
+    }
+    static constexpr int count()
+    {
+        int n = 0;
+        for (int a = -1; a <= H1; ++a)
+            for (int b = -1; b <= H2; ++b)
+                for (int c = 0; c <= H3; ++c)
+                    if (inVX(a, b, c)) ++n;
+        return n;
+    }
+    static constexpr int NVX = count();
+    static constexpr int NQX = (NVX + 3) / 4;
+    static constexpr int NVXP = NQX * 4;
+    // coarse box: c in [-H, C] in c1, c2 and [-H3, C3) in c3
+    static constexpr int C1 = D / T1 + 1, C2 = D / T2 + 1, C3 = D / T3 + 1;
+    static constexpr int B1 = H1 + C1 + 1, B2 = H2 + C2 + 1, B3 = H3 + C3;
+    static constexpr int64_t BOX_TILES = (int64_t)B1 * B2 * B3;
+    static constexpr int64_t BOX_BYTES = BOX_TILES * TILE;
+    static constexpr int64_t W_BYTES = (int64_t)(NV + 1) * 256;  // block NV is all zero
+};
+
+template <int P>
+struct DeltaTableX {
+    uint32_t vpacked[Geo<P>::NV];         // V, for building W
+    uint32_t packed[GeoX<P>::NVXP];       // VX with +1 on c1, c2 (pack3(d1+1, d2+1, d3))
+    int32_t toff[GeoX<P>::NVXP];          // tile-index offset of delta in the box
+    uint32_t widx[GeoX<P>::NVXP][2];      // W block of delta + Delta_s, 16 bits per shift (NV = zero block)
+    uint32_t qmin[GeoX<P>::NQX];          // per quad: min (offset packed), max, largest weight
+    uint32_t qmax[GeoX<P>::NQX];
+    int32_t qwmax[GeoX<P>::NQX];
+    uint32_t wnz[GeoX<P>::NQX];           // bit s: some block of the quad for shift s is nonzero
+};
+
+template <int P>
+constexpr DeltaTableX<P> make_delta_table_x()
+{
+    using X = GeoX<P>;
+    DeltaTableX<P> t{};
+    int nv = 0;
+    int vid[X::H1 + 2][X::H2 + 2][X::H3 + 1] = {};
+    for (int a = 0; a <= X::H1; ++a)
+        for (int b = 0; b <= X::H2; ++b)
+            for (int c = 0; c <= X::H3; ++c) {
+                vid[a][b][c] = -1;
+                if (X::inV(a, b, c)) {
+                    t.vpacked[nv] = pack3(a, b, c);
+                    vid[a][b][c] = nv++;
+                }
+            }
+    int n = 0;
+    const int sh[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
+    for (int a = -1; a <= X::H1; ++a)
+        for (int b = -1; b <= X::H2; ++b)
+            for (int c = 0; c <= X::H3; ++c) {
+                if (!X::inVX(a, b, c)) continue;
+                t.packed[n] = pack3(a + 1, b + 1, c);
+                t.toff[n] = (a * X::B2 + b) * X::B3 + c;
+                uint32_t w[4];
+                for (int s = 0; s < 4; ++s) {
+                    const int aa = a + sh[s][0], bb = b + sh[s][1];
+                    w[s] = X::inV(aa, bb, c) ? (uint32_t)vid[aa][bb][c] : (uint32_t)X::NV;
+                }
+                t.widx[n][0] = w[0] | (w[1] << 16);
+                t.widx[n][1] = w[2] | (w[3] << 16);
+                ++n;
+            }
+    for (; n < X::NVXP; ++n) {
+        t.packed[n] = pack3(1, 1, 0);
+        t.toff[n] = 0;
+        t.widx[n][0] = (uint32_t)X::NV | ((uint32_t)X::NV << 16);
+        t.widx[n][1] = t.widx[n][0];
+    }
+    for (int q = 0; q < X::NQX; ++q) {
+        int lo[3] = {1 << 20, 1 << 20, 1 << 20}, hi[3] = {-(1 << 20), -(1 << 20), -(1 << 20)}, wmax = -(1 << 20);
+        uint32_t nz = 0;
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t v = t.packed[4 * q + i];
+            const int x[3] = {unp0(v) - 1, unp1(v) - 1, unp2(v)};
+            for (int j = 0; j < 3; ++j) {
+                if (x[j] < lo[j]) lo[j] = x[j];
+                if (x[j] > hi[j]) hi[j] = x[j];
+            }
+            const int w = T1 * x[0] + T2 * x[1] + T3 * x[2];
+            if (w > wmax) wmax = w;
+            for (int s = 0; s < 4; ++s) {
+                const uint32_t wi = (t.widx[4 * q + i][s >> 1] >> (16 * (s & 1))) & 0xFFFFu;
+                if (wi != (uint32_t)X::NV) nz |= 1u << s;
+            }
+        }
+        t.qmin[q] = pack3(lo[0] + 1, lo[1] + 1, lo[2]);
+        t.qmax[q] = pack3(hi[0] + 1, hi[1] + 1, hi[2]);
+        t.qwmax[q] = wmax;
+        t.wnz[q] = nz;
+    }
+    return t;
+}
+
 // Number of output tiles with w(c) = 2 c1 + 2 c2 + 4 c3 <= n, c >= 0.
 __host__ __device__ constexpr int64_t tiles_upto(int n)
 {

@@ -11,6 +11,17 @@ namespace qfs {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
 
+// Explicit global-memory accesses: generic (flat) accesses are counted by both
+// the vector-memory and the LDS wait counters, which serialises prefetches
+// against LDS reads.
+#define QFS_GLOBAL __attribute__((address_space(1)))
+__device__ inline v4i gload16(const uint8_t *p) { return *(const QFS_GLOBAL v4i *)(p); }
+__device__ inline v4u gload16u(const uint8_t *p) { return *(const QFS_GLOBAL v4u *)(p); }
+__device__ inline void gstore16(uint8_t *p, v4u v) { *(QFS_GLOBAL v4u *)(p) = v; }
+__device__ inline void gstore4(uint8_t *p, unsigned v) { *(QFS_GLOBAL unsigned *)(p) = v; }
+__device__ inline void gstore1(uint8_t *p, uint8_t v) { *(QFS_GLOBAL uint8_t *)(p) = v; }
+__device__ inline uint8_t gload1(const uint8_t *p) { return *(const QFS_GLOBAL uint8_t *)(p); }
+
 __constant__ B4Table kB4 = make_b4();
 template <int P>
 __constant__ DeltaTable<P> kDT = make_delta_table<P>();
@@ -149,7 +160,7 @@ __device__ inline void theta_full(const uint8_t *__restrict__ dl, const uint8_t 
             const uint8_t *row = dl + kTT<P>.roff[j] + cns_rank(r2 - c2, r3 - c3, r4 - c4) * rsj;
             const uint8_t *av = aperm + kTT<P>.cp_seg[cp];
             for (int k = 0; k < rsj; k += 16)
-                acc = dot16(*(const v4u *)(row + k), *(const v4u *)(av + k), acc);
+                acc = dot16(gload16u(row + k), *(const v4u *)(av + k), acc);
         }
         out[r] = (uint8_t)(acc % P);
     }
@@ -173,7 +184,7 @@ __device__ inline int theta_test(const uint8_t *__restrict__ dl, const uint8_t *
         const int64_t row = kTT<P>.roff[j] +
                             cns_rank(P - 1 - c2, P - 1 - c3, P - 1 - c4) * kTT<P>.rs[j];
         (void)c1;
-        part = dot16(*(const v4u *)(dl + row + (off - kTT<P>.cp_seg[cp])), *(const v4u *)(aperm + off), part);
+        part = dot16(gload16u(dl + row + (off - kTT<P>.cp_seg[cp])), *(const v4u *)(aperm + off), part);
     }
     return block_sum((int)(part % P), red) % P;
 }

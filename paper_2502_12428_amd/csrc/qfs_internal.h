@@ -22,36 +22,77 @@ enum { CNT_COUNT = 0, CNT_POP = 4, CNT_ERR = 8, CNT_WORDS = 64 };
 
 enum { MODE_HEIGHT = 0, MODE_DELTA = 1 };
 
-// Output-tile lists: list k (k = 0..P-1) holds the tiles c >= 0 with
-// 2 c1 + 2 c2 + 4 c3 <= (k+1) d in lexicographic order, packed with pack3().
+// Output-tile lists of the deep kernel (packed with pack3):
+//  base list k (k = 1..P-1): base tiles of the 2x2 super-tiles of output
+//    degree n = (k+1) d: c1, c2 even, w(c) = 2 c1 + 2 c2 + 4 c3 <= n;
+//  shell list k (k = 0..P-2): all tiles c >= 0 of the box with
+//    w(c) <= (k+2) d + 4, the region the next product reads.
 template <int P>
 struct PlanTable {
-    int64_t len[P];
-    int64_t off[P + 1];
+    int64_t blen[P], boff[P], flen[P], foff[P];
+    int64_t words;
 };
+template <int P>
+constexpr int64_t base_tiles(int n)
+{
+    int64_t cnt = 0;
+    for (int a = 0; T1 * a <= n; a += 2)
+        for (int b = 0; T1 * a + T2 * b <= n; b += 2) cnt += (n - T1 * a - T2 * b) / T3 + 1;
+    return cnt;
+}
+template <int P>
+constexpr int64_t shell_tiles(int m)
+{
+    using X = GeoX<P>;
+    int64_t cnt = 0;
+    for (int a = 0; a <= X::C1 && T1 * a <= m; ++a)
+        for (int b = 0; b <= X::C2 && T1 * a + T2 * b <= m; ++b) {
+            int top = (m - T1 * a - T2 * b) / T3;
+            if (top > X::C3 - 1) top = X::C3 - 1;
+            cnt += top + 1;
+        }
+    return cnt;
+}
 template <int P>
 constexpr PlanTable<P> make_plan_table()
 {
+    constexpr int d = 4 * (P - 1);
     PlanTable<P> t{};
-    t.off[0] = 0;
+    int64_t o = 0;
     for (int k = 0; k < P; ++k) {
-        t.len[k] = tiles_upto((k + 1) * 4 * (P - 1));
-        t.off[k + 1] = t.off[k] + t.len[k];
+        t.boff[k] = o;
+        t.blen[k] = k >= 1 ? base_tiles<P>((k + 1) * d) : 0;
+        o += t.blen[k];
     }
+    for (int k = 0; k < P; ++k) {
+        t.foff[k] = o;
+        t.flen[k] = k <= P - 2 ? shell_tiles<P>((k + 2) * d + 4) : 0;
+        o += t.flen[k];
+    }
+    t.words = o;
     return t;
 }
 template <int P>
 constexpr int64_t plan_words()
 {
-    return make_plan_table<P>().off[P];
+    return make_plan_table<P>().words;
 }
 
-// Per persistent workgroup ("slot") of the deep kernel: the W blocks, two
-// tile boxes for the chain g~^k, and Delta in the Cartier-split layout.
+// W blocks live in LDS when they fit next to the other per-surface tables.
+template <int P>
+__host__ __device__ constexpr bool w_in_lds()
+{
+    return GeoX<P>::W_BYTES <= 100 * 1024;
+}
+
+// Per persistent workgroup ("slot") of the deep kernel: the W blocks when
+// they do not fit in LDS, two tile boxes for the chain g~^k, and Delta in
+// the Cartier-split layout.
 template <int P>
 __host__ __device__ constexpr size_t slot_bytes()
 {
-    return align256(Geo<P>::W_BYTES) + 2 * align256(Geo<P>::BOX_BYTES) + align256(ThetaGeo<P>::BYTES);
+    return (w_in_lds<P>() ? 0 : align256(GeoX<P>::W_BYTES)) + 2 * align256(GeoX<P>::BOX_BYTES) +
+           align256(ThetaGeo<P>::BYTES);
 }
 
 struct BatchLayout {

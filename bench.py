@@ -53,6 +53,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=384)
     ap.add_argument("--plain-sample", type=int, default=48)
     ap.add_argument("--no-baselines", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="before the timed region, copy this many MiB device-to-device once: a plain copy "
+                         "kernel of known size whose memory counters scale the profiler's byte counts")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the height pipeline has no cross-GPU step and this build runs on a "
@@ -74,6 +77,13 @@ def main():
     print("bench: workload %s, batch %d, warmup %d, steps %d" % (args.workload, B, args.warmup, args.steps),
           file=sys.stderr, flush=True)
 
+    if args.calibrate_copy_mb > 0:
+        src = torch.ones(args.calibrate_copy_mb << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         h = qfs.height(f, pt, max_p=p, workspace=ws)
     torch.cuda.synchronize()

@@ -193,8 +193,10 @@ struct DeepLds {
     static constexpr int off_g = off_w + WB;
     static constexpr int off_aperm = off_g + LGA;
     static constexpr int off_toff = off_aperm + APA;
-    static constexpr int off_widx = off_toff + 4 * X::NVXP;
-    static constexpr int off_red = off_widx + 8 * X::NVXP;
+    static constexpr int off_widx = off_toff + 4 * (X::NVXP + 4);
+    static constexpr int off_qbox = off_widx + 8 * (X::NVXP + 4);
+    static constexpr int off_qlist = off_qbox + 8 * X::NQX;
+    static constexpr int off_red = off_qlist + ((2 * (X::NQX + 1) * (DEEP_NT / 64) + 15) / 16 * 16);
     static constexpr int bytes = off_red + 4 * 64;
 };
 
@@ -264,7 +266,6 @@ __device__ void zero_shell(const uint32_t *list, int ntiles, int n, uint8_t *A)
 
 struct EpiCtx {
     int mode;
-    uint8_t *dl;      // MODE_HEIGHT: Delta in the Cartier-split layout
     uint8_t *dout;    // MODE_DELTA: Delta in CNS order for this surface
     const uint8_t *g; // LDS
     int *err;         // LDS flag
@@ -272,30 +273,34 @@ struct EpiCtx {
 
 // Delta_1 epilogue for the four positions s = 4 kg + v of output tile c:
 // D = (g~^p - sum_J b_J^p x^(pJ)) / p mod p (Algorithm 1, lines 3-5).
+// Returns the four values packed in a word (byte v for position 4 kg + v;
+// positions beyond degree D give 0).  MODE_DELTA also scatters them to the
+// caller's array in CNS order.
 template <int P>
-__device__ __attribute__((always_inline)) inline void epilogue(int c1, int c2, int c3, int kg, v4i acc,
-                                                               const EpiCtx &ec)
+__device__ __attribute__((always_inline)) inline unsigned epilogue(int c1, int c2, int c3, int kg, v4i acc,
+                                                                   const EpiCtx &ec)
 {
     constexpr int P2 = P * P, D = 4 * P * (P - 1);
     const int x1 = T1 * c1 + (kg >> 1), x2 = T2 * c2 + (kg & 1);
+    const bool j12 = (x1 % P == 0) && (x2 % P == 0);
+    unsigned packed = 0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int x3 = T3 * c3 + v;
         const int x4 = D - x1 - x2 - x3;
         if (x4 < 0) continue;
         int val = acc[v] % P2;
-        if (x1 % P == 0 && x2 % P == 0 && x3 % P == 0) {
+        if (j12 && x3 % P == 0) {
             const int bj = ec.g[cns_rank(x2 / P, x3 / P, x4 / P)];
             val -= pow_p_mod_p2<P>(bj);
             if (val < 0) val += P2;
         }
         if (val % P) *ec.err = 1;
-        const uint8_t dv = (uint8_t)(val / P);
-        if (ec.mode == MODE_HEIGHT)
-            gstore1(ec.dl + theta_addr<P>(x1, x2, x3, x4), dv);
-        else
-            gstore1(ec.dout + cns_rank(x2, x3, x4), dv);
+        const unsigned dv = (unsigned)(val / P);
+        packed |= dv << (8 * v);
+        if (ec.mode == MODE_DELTA) gstore1(ec.dout + cns_rank(x2, x3, x4), (uint8_t)dv);
     }
+    return packed;
 }
 
 // One wave computes NB groups of 16 base tiles and their four shifts, i.e.
@@ -306,7 +311,7 @@ __device__ __attribute__((always_inline)) inline void epilogue(int c1, int c2, i
 template <int P>
 __device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *list, int nbase, int gs, int nk, const uint8_t *W,
                          const uint8_t *__restrict__ Ain, uint8_t *Aout, bool last, const int *toff_l,
-                         const uint32_t *widx_l, const EpiCtx &ec)
+                         const uint32_t *widx_l, const uint32_t *qbox_l, uint16_t *qlist, const EpiCtx &ec)
 {
     using X = GeoX<P>;
     constexpr int NB = DEEP_NB;
@@ -338,59 +343,90 @@ __device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *l
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[s][b] = v4i{0, 0, 0, 0};
 
-    // bit b set: the input tiles of group b for quad q can be nonzero (scalar bounding-box test)
-    auto need_mask = [&](int q) -> uint32_t {
-        const uint32_t qmin = kDX<P>.qmin[q];
-        const int qw = kDX<P>.qwmax[q];
-        const int qm1 = unp0(qmin) - 1, qm2 = unp1(qmin) - 1, qm3 = unp2(qmin);
-        uint32_t m = 0;
+    // Bounding box of the set's tiles.  A quad whose input tiles q - delta all lie
+    // outside A_k (a negative coordinate, or weight above deg A_k) contributes
+    // nothing and is skipped.  For the quads that are processed, every group and
+    // every shift is multiplied: tiles outside A_k read the zero halo or the
+    // zeroed shell and the zero W block adds nothing, so the products stay exact
+    // and the loop has no branches around the matrix instructions.
+    int smax1 = 0, smax2 = 0, smax3 = 0, swmin = 1 << 30;
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-            if (gex[b] && gmax1[b] >= qm1 && gmax2[b] >= qm2 && gmax3[b] >= qm3 && gwmin[b] - qw <= nk) m |= 1u << b;
-        return (uint32_t)uniform((int)m);
-    };
+    for (int b = 0; b < NB; ++b)
+        if (gex[b]) {
+            smax1 = max(smax1, gmax1[b]);
+            smax2 = max(smax2, gmax2[b]);
+            smax3 = max(smax3, gmax3[b]);
+            swmin = min(swmin, gwmin[b]);
+        }
+    // the quads this set needs, in order, into the wave's list in LDS
+    int nq = 0;
+    for (int q0 = 0; q0 < X::NQX; q0 += 64) {
+        const int q = q0 + lane;
+        bool nd = false;
+        if (q < X::NQX) {
+            const uint32_t qmin = qbox_l[2 * q];
+            nd = smax1 >= (int)unp0(qmin) - 1 && smax2 >= (int)unp1(qmin) - 1 && smax3 >= (int)unp2(qmin) &&
+                 swmin - (int)qbox_l[2 * q + 1] <= nk;
+        }
+        const uint64_t m = __ballot(nd);
+        if (nd) qlist[nq + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)q;
+        nq += __popcll(m);
+    }
+    nq = uniform(nq);
+    // pad to an even count with the null quad (index NQX: offset 0, zero W blocks)
+    if (nq & 1) {
+        if (lane == 0) qlist[nq] = (uint16_t)X::NQX;
+        ++nq;
+    }
 
-    v4i bf[NB], bfn[NB];
+    // byte offsets of the tiles inside the box fit in 32 bits
+    uint32_t boff[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) bf[b] = bfn[b] = v4i{0, 0, 0, 0};
-    int q = 0;
-    uint32_t need = 0;
-    while (q < X::NQX && !(need = need_mask(q))) ++q;
-    // every group's fragment is loaded (its address is inside the box even when the group
-    // is absent or skipped), so the number of loads in flight is fixed per iteration
-    if (q < X::NQX) {
-        const int to = toff_l[4 * q + kg];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) bf[b] = gload16(Ain + (base[b] - to) * 16);
-    }
-    while (q < X::NQX) {
-        // issue the next needed quad's input loads before this quad's products
-        int qn = q + 1;
-        uint32_t need_n = 0;
-        while (qn < X::NQX && !(need_n = need_mask(qn))) ++qn;
-        {
-            // issued on every iteration (the last one reloads quad q) so that the wait
-            // before this quad's products is the same on every path
-            const int to = toff_l[4 * (qn < X::NQX ? qn : q) + kg];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) bfn[b] = gload16(Ain + (base[b] - to) * 16);
+    for (int b = 0; b < NB; ++b) boff[b] = (uint32_t)base[b] * 16u;
+    const uint32_t wrow = (uint32_t)col * 16u;
+    // input fragments of the list entry i (clamped to the last entry)
+#define QFS_LOAD_B(BF, I)                                                                          \
+    do {                                                                                           \
+        const int q_ = uniform(qlist[(I) < nq ? (I) : nq - 1]);                                    \
+        const uint32_t to_ = (uint32_t)toff_l[4 * q_ + kg] * 16u;                                  \
+        _Pragma("unroll") for (int b = 0; b < NB; ++b) BF[b] = gload16(Ain + (boff[b] - to_));     \
+    } while (0)
+    // W fragments of list entry i for the four shifts, then the 4 x NB products
+#define QFS_PRODUCTS(BF, I)                                                                                \
+    do {                                                                                                   \
+        const int q_ = uniform(qlist[I]);                                                                  \
+        const uint32_t w01_ = widx_l[2 * (4 * q_ + kg)], w23_ = widx_l[2 * (4 * q_ + kg) + 1];              \
+        v4i wf_[4];                                                                                        \
+        _Pragma("unroll") for (int s = 0; s < 4; ++s)                                                      \
+        {                                                                                                  \
+            const uint32_t wi = ((s < 2 ? w01_ : w23_) >> (16 * (s & 1))) & 0xFFFFu;                        \
+            wf_[s] = w_in_lds<P>() ? *(const v4i *)(W + wi * 256u + wrow) : gload16(W + wi * 256u + wrow);  \
+        }                                                                                                  \
+        _Pragma("unroll") for (int s = 0; s < 4; ++s)                                                      \
+            _Pragma("unroll") for (int b = 0; b < NB; ++b)                                                 \
+                acc[s][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(wf_[s], BF[b], acc[s][b], 0, 0, 0);       \
+    } while (0)
+
+    // two fragment sets alternate; each is refilled two entries ahead of its use
+    if (nq > 0) {
+        v4i bfa[NB], bfb[NB];
+        QFS_LOAD_B(bfa, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        QFS_LOAD_B(bfb, 1);
+        __builtin_amdgcn_sched_barrier(0);
+        for (int i = 0; i < nq; i += 2) {
+            QFS_PRODUCTS(bfa, i);
+            __builtin_amdgcn_sched_barrier(0);
+            QFS_LOAD_B(bfa, i + 2);
+            __builtin_amdgcn_sched_barrier(0);
+            QFS_PRODUCTS(bfb, i + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            QFS_LOAD_B(bfb, i + 3);
+            __builtin_amdgcn_sched_barrier(0);
         }
-        const uint32_t nz = kDX<P>.wnz[q];
-        const uint32_t w01 = widx_l[2 * (4 * q + kg)], w23 = widx_l[2 * (4 * q + kg) + 1];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            if (!((nz >> s) & 1)) continue;
-            const uint32_t wi = ((s < 2 ? w01 : w23) >> (16 * (s & 1))) & 0xFFFFu;
-            const v4i wf = w_in_lds<P>() ? *(const v4i *)(W + wi * 256 + col * 16) : gload16(W + wi * 256 + col * 16);
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-                if ((need >> b) & 1) acc[s][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(wf, bf[b], acc[s][b], 0, 0, 0);
-        }
-        q = qn;
-        need = need_n;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) bf[b] = bfn[b];
     }
+#undef QFS_LOAD_B
+#undef QFS_PRODUCTS
 
     constexpr int64_t SH1 = (int64_t)X::B2 * X::B3, SH2 = X::B3;
 #pragma unroll
@@ -400,14 +436,54 @@ __device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *l
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int d1 = s & 1, d2 = s >> 1;
+            unsigned packed = 0;
             if (!last) {
-                unsigned packed = 0;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) packed |= (unsigned)(acc[s][b][v] % P2) << (8 * v);
-                gstore4(Aout + (base[b] + d1 * SH1 + d2 * SH2) * 16 + 4 * kg, packed);
             } else {
-                epilogue<P>(c1 + d1, c2 + d2, c3, kg, acc[s][b], ec);
+                packed = epilogue<P>(c1 + d1, c2 + d2, c3, kg, acc[s][b], ec);
             }
+            gstore4(Aout + (base[b] + d1 * SH1 + d2 * SH2) * 16 + 4 * kg, packed);
+        }
+    }
+}
+
+// c(theta(a)) = sum_c a[c] Delta[(p+1) e - c] mod p, read from Delta's tile box:
+// the only coefficient of theta(a) the height test needs (Section 3.4).
+template <int P>
+__device__ int theta_test_box(const uint8_t *dbox, const uint8_t *a, int *red)
+{
+    constexpr int d = 4 * (P - 1), LG = (int)num_mono(d), E = P * P - 1;
+    unsigned part = 0;
+    for (int c = threadIdx.x; c < LG; c += blockDim.x) {
+        const unsigned av = a[c];
+        if (!av) continue;
+        int c1, c2, c3, c4;
+        cns_unrank(d, c, c1, c2, c3, c4);
+        const int x1 = E - c1, x2 = E - c2, x3 = E - c3;
+        const int64_t t = box_tile<P>(x1 >> 1, x2 >> 1, x3 >> 2);
+        part += av * gload1(dbox + t * 16 + (x1 & 1) * 8 + (x2 & 1) * 4 + (x3 & 3));
+    }
+    return block_sum((int)(part % P), red) % P;
+}
+
+// Copy Delta from its tile box into the Cartier-split layout used by theta_full.
+template <int P>
+__device__ void box_to_theta(const uint8_t *dbox, const uint32_t *list, int nbase, uint8_t *dl)
+{
+    constexpr int D = 4 * P * (P - 1);
+    for (int i = threadIdx.x; i < nbase * 4; i += blockDim.x) {
+        const uint32_t t = list[i >> 2];
+        const int s = i & 3;
+        const int c1 = unp0(t) + (s & 1), c2 = unp1(t) + (s >> 1), c3 = unp2(t);
+        const v4u tile = gload16u(dbox + box_tile<P>(c1, c2, c3) * 16);
+#pragma unroll
+        for (int pos = 0; pos < 16; ++pos) {
+            const int x1 = T1 * c1 + (pos >> 3), x2 = T2 * c2 + ((pos >> 2) & 1), x3 = T3 * c3 + (pos & 3);
+            const int x4 = D - x1 - x2 - x3;
+            if (x4 < 0) continue;
+            const unsigned word = pos < 4 ? tile.x : pos < 8 ? tile.y : pos < 12 ? tile.z : tile.w;
+            gstore1(dl + theta_addr<P>(x1, x2, x3, x4), (uint8_t)((word >> (8 * (pos & 3))) & 255u));
         }
     }
 }
@@ -425,6 +501,8 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
     uint8_t *aperm = lds + L::off_aperm;
     int *toff_l = (int *)(lds + L::off_toff);
     uint32_t *widx_l = (uint32_t *)(lds + L::off_widx);
+    uint32_t *qbox_l = (uint32_t *)(lds + L::off_qbox);
+    uint16_t *qlist_l = (uint16_t *)(lds + L::off_qlist);
     int *red = (int *)(lds + L::off_red);
     __shared__ int s_pos, s_err;
 
@@ -443,6 +521,14 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
         toff_l[i] = kDX<P>.toff[i];
         widx_l[2 * i] = kDX<P>.widx[i][0];
         widx_l[2 * i + 1] = kDX<P>.widx[i][1];
+    }
+    if (tid < 4) {  // the null quad
+        toff_l[X::NVXP + tid] = 0;
+        widx_l[2 * (X::NVXP + tid)] = widx_l[2 * (X::NVXP + tid) + 1] = (uint32_t)X::NV | ((uint32_t)X::NV << 16);
+    }
+    for (int i = tid; i < X::NQX; i += DEEP_NT) {
+        qbox_l[2 * i] = kDX<P>.qmin[i];
+        qbox_l[2 * i + 1] = (uint32_t)kDX<P>.qwmax[i];
     }
     // the halo (tiles with a negative coordinate) of both boxes is read as zero and never written
     for (int64_t t = tid; t < X::BOX_TILES; t += DEEP_NT) {
@@ -473,7 +559,6 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
 
         EpiCtx ec;
         ec.mode = a.mode;
-        ec.dl = dl;
         ec.dout = a.delta_out ? a.delta_out + (size_t)surf * PR::len_D : nullptr;
         ec.g = g_l;
         ec.err = &s_err;
@@ -485,7 +570,7 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
             const bool last = (k == P - 1);
             const uint32_t *list = a.plan + kPT<P>.boff[k];
             for (int gs = wave; gs < nsets; gs += DEEP_NW)
-                mfma_set<P>(list, nbase, gs, k * d, W, Ain, Aout, last, toff_l, widx_l, ec);
+                mfma_set<P>(list, nbase, gs, k * d, W, Ain, Aout, last, toff_l, widx_l, qbox_l, qlist_l + wave * (X::NQX + 1), ec);
             if (!last) zero_shell<P>(a.plan + kPT<P>.foff[k], (int)kPT<P>.flen[k], (k + 1) * d, Aout);
             __syncthreads();
         }
@@ -501,16 +586,22 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
         }
         // Algorithm 3's loop: the test reads c(theta(a)) only; theta(a) in full
         // is needed only when the surface goes on to the next h.
+        const uint8_t *dbox = buf[(P - 1) & 1];
         int h = 0;
+        bool split = false;
         for (int hh = 2; hh <= a.bound; ++hh) {
-            build_aperm<P>(g_l, aperm);
-            __syncthreads();
-            const int t = theta_test<P>(dl, aperm, red);
+            const int t = theta_test_box<P>(dbox, g_l, red);
             if (t != 0) {
                 h = hh;
                 break;
             }
             if (hh == a.bound) break;
+            if (!split) {
+                box_to_theta<P>(dbox, a.plan + kPT<P>.boff[P - 1], (int)kPT<P>.blen[P - 1], dl);
+                split = true;
+            }
+            build_aperm<P>(g_l, aperm);
+            __syncthreads();
             theta_full<P>(dl, aperm, g_l);
             __syncthreads();
         }
@@ -558,10 +649,11 @@ static int64_t mfma_count_p()
             for (int c2 = 0; T1 * c1 + T2 * c2 <= n; c2 += 2)
                 for (int c3 = 0; T1 * c1 + T2 * c2 + T3 * c3 <= n; ++c3) tiles.push_back(pack3(c1, c2, c3));
         const int nt = (int)tiles.size();
-        for (int g0 = 0; g0 < nt; g0 += 16) {
+        const int ngroups = (nt + 15) / 16;
+        for (int gs = 0; gs * DEEP_NB < ngroups; ++gs) {
             int m1 = 0, m2 = 0, m3 = 0, wmin = 1 << 30;
-            for (int j = 0; j < 16 && g0 + j < nt; ++j) {
-                const uint32_t t = tiles[g0 + j];
+            for (int g = gs * DEEP_NB * 16; g < std::min(nt, (gs + 1) * DEEP_NB * 16); ++g) {
+                const uint32_t t = tiles[g];
                 m1 = std::max(m1, unp0(t));
                 m2 = std::max(m2, unp1(t));
                 m3 = std::max(m3, unp2(t));
@@ -569,8 +661,9 @@ static int64_t mfma_count_p()
             }
             for (int q = 0; q < X::NQX; ++q) {
                 const uint32_t qm = DX.qmin[q];
-                if (m1 >= unp0(qm) - 1 && m2 >= unp1(qm) - 1 && m3 >= unp2(qm) && wmin - DX.qwmax[q] <= nk)
-                    total += __builtin_popcount(DX.wnz[q]);
+                if (m1 >= (int)unp0(qm) - 1 && m2 >= (int)unp1(qm) - 1 && m3 >= (int)unp2(qm) &&
+                    wmin - DX.qwmax[q] <= nk)
+                    total += 4 * DEEP_NB;
             }
         }
     }

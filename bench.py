@@ -27,25 +27,25 @@ sys.path.insert(0, ROOT)
 METRIC = "quartics height-classified/sec at p=7 (batched int8-MFMA vs plain), bit-exact"
 INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix peak, 5.0 POP/s
 
-# HBM traffic of the deep kernel on the p7_batch65536 workload from two
+# HBM traffic of the deep kernels on the p7_batch65536 workload from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each
-# scaled by what the same counter read for a 512 MiB device-to-device copy
-# (FETCH x 1.9998, WRITE x 1.0).  Valid only for the kernel sources they were
-# taken on; any change to those sources reports null until re-measured.
+# scaled by what the same counter read for a 512 MiB device-to-device copy.
+# Valid only for the kernel sources they were taken on; any change to those
+# sources reports null until re-measured.
 TRAFFIC_SOURCES = ("qfs_batched.hip", "qfs_device.h", "qfs_common.h", "qfs_internal.h")
 TRAFFIC = {
     "workload": "p7_batch65536",
-    "sources_sha256": "d4b61a1b179fdc5afe27734e924d5d1b3949eb405e6ed3c75b993bc097dd9327",
-    "fetch_kib": 311307806.4375, "fetch_scale": 524288.0 / 262170.625,
-    "write_kib": 66872266.375, "write_scale": 1.0,
-    "profile": "profiles/k_deep7_p7_batch65536_counters.md",
+    "sources_sha256": None,
+    "fetch_scale": None, "write_scale": None,
+    "kernels": {},  # kernel name -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
+    "profile": None,
 }
 
 
-def measured_traffic(workload):
-    """Calibrated HBM bytes per deep-kernel launch, or None if stale or for another workload."""
+def measured_traffic(workload, kernel):
+    """Calibrated HBM bytes per launch of `kernel`, or None if stale, not measured or another workload."""
     import hashlib
-    if workload != TRAFFIC["workload"]:
+    if workload != TRAFFIC["workload"] or kernel not in TRAFFIC["kernels"] or not TRAFFIC["sources_sha256"]:
         return None
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
@@ -53,7 +53,37 @@ def measured_traffic(workload):
             h.update(fh.read())
     if h.hexdigest() != TRAFFIC["sources_sha256"]:
         return None
-    return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
+    fetch, write = TRAFFIC["kernels"][kernel]
+    return 1024.0 * (fetch * TRAFFIC["fetch_scale"] + write * TRAFFIC["write_scale"])
+
+
+def count_terms_below(X, d):
+    """For each row x of X (4 exponents): the number of t >= 0 with |t| = d and t <= x
+    componentwise, by inclusion-exclusion over the coordinates that exceed x."""
+    import numpy as np
+    tot = np.zeros(len(X), dtype=np.int64)
+    for S in range(16):
+        idx = [i for i in range(4) if S >> i & 1]
+        m = d - sum(X[:, i] + 1 for i in idx) if idx else np.full(len(X), d, dtype=np.int64)
+        tot += (-1) ** len(idx) * np.where(m >= 0, (m + 3) * (m + 2) * (m + 1) // 6, 0)
+    return tot
+
+
+def band_macs(p):
+    """Multiply-adds the capped chain needs: for k = 1..p-1 the products g~[t] A_k[x-t] over the
+    outputs x of A_(k+1) with all four exponents <= p^2-1 (last step: the window p^2-1-d..p^2-1)."""
+    import numpy as np
+    d, E = 4 * (p - 1), p * p - 1
+    tot = 0
+    for k in range(1, p):
+        n = (k + 1) * d
+        lo = E - d if k == p - 1 else 0
+        r = np.arange(lo, E + 1, dtype=np.int64)
+        x1, x2, x3 = (a.ravel() for a in np.meshgrid(r, r, r, indexing="ij"))
+        x4 = n - x1 - x2 - x3
+        m = (x4 >= lo) & (x4 <= E)
+        tot += int(count_terms_below(np.stack([x1[m], x2[m], x3[m], x4[m]], 1), d).sum())
+    return tot
 
 
 def delta1_macs(p):
@@ -62,14 +92,12 @@ def delta1_macs(p):
     return sum(comb(d * k + 3, 3) * comb(d + 3, 3) for k in range(1, p))
 
 
-def theta_macs(p, h, bound=10):
-    """theta work of one deep surface with height h: (tests) x len_g + (full maps) x len_g^2."""
+def theta_macs(p, h, skip_first, bound=10):
+    """theta work of one surface of height h (0: infinite) in the full-chain kernel:
+    (tests) x len_g + (full maps) x len_g^2; skip_first: the capped chain did the first test."""
     lg = comb(4 * p - 1, 3)
-    if h == 0:
-        tests, full = bound - 1, bound - 2
-    else:
-        tests, full = h - 1, h - 2
-    return tests * lg + max(full, 0) * lg * lg
+    tests, full = (bound - 1, bound - 2) if h == 0 else (h - 1, h - 2)
+    return (tests - (1 if skip_first else 0)) * lg + max(full, 0) * lg * lg
 
 
 WORKLOADS = {
@@ -163,25 +191,48 @@ def main():
     if os.path.exists(gold):
         parity = bool(np.array_equal(np.load(gold)["heights"].astype(np.int32), heights))
 
-    # the dominant deep kernel (the prime whose deep launch takes longest)
+    # the deep kernels: per prime the capped chain (every deep surface) and the
+    # full chain with the theta loop (surfaces of height > 2)
     per_call = {k: v / max(calls, 1) for k, v in stage_ms.items()}
-    pd = max((q for q in (3, 5, 7, 11) if (P == q).any()), key=lambda q: per_call["deep_p%d" % q])
-    deep_ms = per_call["deep_p%d" % pd]
+    band_on = qfs.get_option("height_band") == 1
     is_deep = (heights == 0) | (heights >= 2)
-    deep = heights[is_deep & (P == pd)]
-    n_deep = int(deep.size)
-    useful = n_deep * delta1_macs(pd) + sum(theta_macs(pd, int(x)) for x in deep)
-    achieved = 2.0 * useful / (deep_ms * 1e-3) / 1e12 if deep_ms > 0 else 0.0
-    executed = 2.0 * n_deep * qfs.mfma_per_surface(pd) * 16384 / (deep_ms * 1e-3) / 1e12 if deep_ms > 0 else 0.0
+    kernels = {}
+    for q in (3, 5, 7, 11):
+        hq = heights[is_deep & (P == q)]
+        beyond = hq[(hq == 0) | (hq >= 3)] if band_on else hq
+        lg = comb(4 * q - 1, 3)
+        if band_on and hq.size:
+            kernels["k_deep<%d, true>" % q] = {
+                "ms": per_call["band_p%d" % q], "surfaces": int(hq.size),
+                "useful_ops": 2.0 * hq.size * (band_macs(q) + lg),
+                "mfma": int(hq.size) * qfs.mfma_per_surface(q, band=True)}
+        if beyond.size:
+            kernels["k_deep<%d, false>" % q] = {
+                "ms": per_call["deep_p%d" % q], "surfaces": int(beyond.size),
+                "useful_ops": 2.0 * (beyond.size * delta1_macs(q) +
+                                     sum(theta_macs(q, int(x), band_on) for x in beyond)),
+                "mfma": int(beyond.size) * qfs.mfma_per_surface(q)}
+    for name, kd in kernels.items():
+        sec = kd["ms"] * 1e-3
+        kd["achieved_tops"] = kd["useful_ops"] / sec / 1e12 if sec > 0 else 0.0
+        kd["executed_mfma_tops"] = kd["mfma"] * 32768.0 / sec / 1e12 if sec > 0 else 0.0
+        kd["executed_mfma_frac"] = kd["executed_mfma_tops"] / INT8_PEAK_TOPS
+        kd["traffic"] = measured_traffic(args.workload, name)
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    kd = kernels[dom]
+    pd = int(dom.split("<")[1].split(",")[0])
+    n_deep = int(is_deep.sum())
     per_prime = {}
     for q in (3, 5, 7, 11):
         n_q = int((P == q).sum())
         if n_q:
-            t_q = per_call["deep_p%d" % q] + per_call["stage1"] * n_q / B + per_call["plan"] / 4
+            t_q = (per_call["band_p%d" % q] + per_call["deep_p%d" % q] + per_call["stage1"] * n_q / B +
+                   per_call["plan"] / 4)
             per_prime[str(q)] = {"surfaces": n_q, "deep_surfaces": int((is_deep & (P == q)).sum()),
-                                 "deep_kernel_ms": per_call["deep_p%d" % q],
+                                 "band_kernel_ms": per_call["band_p%d" % q],
+                                 "full_kernel_ms": per_call["deep_p%d" % q],
                                  "quartics_per_s": n_q / (t_q * 1e-3) if t_q > 0 else None}
-    traffic = measured_traffic(args.workload)
+    traffic = kd["traffic"]
     print("bench: %.1f ms/step, stages %s, deep surfaces %d" % (1e3 * elapsed / args.steps,
           {k: round(v, 3) for k, v in per_call.items()}, n_deep), file=sys.stderr, flush=True)
 
@@ -205,20 +256,21 @@ def main():
         "parity_vs_oracle": parity,
         "roofline": {
             "bound": "mfma",
-            "kernel": "k_deep<%d> (Delta_1 chain on v_mfma_i32_16x16x64_i8 + theta)" % pd,
-            "achieved": achieved,
+            "kernel": dom,
+            "achieved": kd["achieved_tops"],
             "peak": INT8_PEAK_TOPS,
             "unit": "TOP/s",
-            "frac": achieved / INT8_PEAK_TOPS,
+            "frac": kd["achieved_tops"] / INT8_PEAK_TOPS,
             "traffic": traffic,
             "traffic_unit": "bytes/launch",
-            "traffic_gbps": traffic / (deep_ms * 1e-3) / 1e9 if traffic and deep_ms > 0 else None,
+            "traffic_gbps": traffic / (kd["ms"] * 1e-3) / 1e9 if traffic and kd["ms"] > 0 else None,
             "traffic_profile": TRAFFIC["profile"] if traffic else None,
-            "kernel_ms_per_launch": deep_ms,
-            "useful_ops_per_launch": 2.0 * useful,
-            "deep_surfaces_per_launch": n_deep,
-            "executed_mfma_tops": executed,
-            "executed_mfma_frac": executed / INT8_PEAK_TOPS,
+            "kernel_ms_per_launch": kd["ms"],
+            "useful_ops_per_launch": kd["useful_ops"],
+            "surfaces_per_launch": kd["surfaces"],
+            "executed_mfma_tops": kd["executed_mfma_tops"],
+            "executed_mfma_frac": kd["executed_mfma_frac"],
+            "kernels": kernels,
         },
         "stage_ms_per_step": per_call,
         "per_prime": per_prime,

@@ -140,17 +140,34 @@ int qfs_height_plain(int p, int batch, const uint8_t *f, int bound, int32_t *hei
 /* ------------------------------------------------------------------------
  * Stage timing (diagnostics).  While enabled, every qfs_height call records
  * hipEvents on its stream around its stages; qfs_profile_collect waits for
- * the recorded events, writes the summed milliseconds per stage into ms[0..5]
- * (0 stage 1, 1 plans, 2..5 deep kernels for p = 3, 5, 7, 11) and the number
- * of calls into *calls, and clears the record.  Host pointers.
+ * the recorded events, writes the summed milliseconds per stage into
+ * ms[0..QFS_PROFILE_STAGES-1] and the number of calls into *calls, and clears
+ * the record.  Stages: 0 stage 1 (g and Fedder's test), 1 plans, 2..5 the
+ * capped-chain launches for p = 3, 5, 7, 11, 6..9 the full-chain launches
+ * (with the theta loop) for p = 3, 5, 7, 11.  Host pointers.
  * ---------------------------------------------------------------------- */
+#define QFS_PROFILE_STAGES 10
 int qfs_profile_enable(int on);
-int qfs_profile_collect(double ms[6], int *calls);
+int qfs_profile_collect(double ms[QFS_PROFILE_STAGES], int *calls);
 
 /* Matrix-core instructions (v_mfma_i32_16x16x64_i8, 16,384 multiply-adds
- * each) that the Delta_1 product issues for one surface at prime p; the
- * count depends only on p.  -1 for an unsupported p. */
-int64_t qfs_mfma_per_surface(int p);
+ * each) that the g~^p product issues for one surface at prime p: pass 0 is
+ * the full chain (qfs_delta1, and qfs_height for surfaces of height > 2),
+ * pass 1 the capped chain qfs_height runs first for every surface that fails
+ * Fedder's test.  The count depends only on p and pass; -1 for an
+ * unsupported p or pass. */
+int64_t qfs_mfma_per_surface(int p, int pass);
+
+/* Process-wide options (host strings; affect calls enqueued afterwards).
+ *   "height_band" (default 1): qfs_height decides h = 2 with the capped
+ *     chain, which forms only the coefficients of Delta_1 that the first
+ *     theta test reads (Section 3.4: c(theta(g)) = sum_c g[c] Delta[(p+1)e-c]),
+ *     and runs the full chain only for surfaces of height > 2.  0 runs the
+ *     full chain for every surface.  Heights are the same either way.
+ * qfs_set_option returns QFS_OK or QFS_EINVAL (unknown name or value);
+ * qfs_get_option returns the value, or QFS_EINVAL for an unknown name. */
+int qfs_set_option(const char *name, int64_t value);
+int64_t qfs_get_option(const char *name);
 
 /* Message for the last error returned in the calling thread ("" if none). */
 const char *qfs_last_error(void);

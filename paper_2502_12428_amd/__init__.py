@@ -34,7 +34,8 @@ EXPORTS = (
     "qfs_num_monomials", "qfs_monomial_rank", "qfs_monomial_unrank", "qfs_len_g", "qfs_len_delta",
     "qfs_delta1_workspace_bytes", "qfs_delta1", "qfs_theta_workspace_bytes", "qfs_theta",
     "qfs_height_workspace_bytes", "qfs_height", "qfs_height_plain_workspace_bytes", "qfs_height_plain",
-    "qfs_profile_enable", "qfs_profile_collect", "qfs_mfma_per_surface", "qfs_last_error", "qfs_shutdown",
+    "qfs_profile_enable", "qfs_profile_collect", "qfs_mfma_per_surface", "qfs_set_option", "qfs_get_option",
+    "qfs_last_error", "qfs_shutdown",
 )
 
 
@@ -72,7 +73,9 @@ def lib():
     L.qfs_height_plain.argtypes, L.qfs_height_plain.restype = [i32, i32, vp, i32, vp, vp, sz, vp], i32
     L.qfs_profile_enable.argtypes, L.qfs_profile_enable.restype = [i32], i32
     L.qfs_profile_collect.argtypes, L.qfs_profile_collect.restype = [vp, vp], i32
-    L.qfs_mfma_per_surface.argtypes, L.qfs_mfma_per_surface.restype = [i32], i64
+    L.qfs_mfma_per_surface.argtypes, L.qfs_mfma_per_surface.restype = [i32, i32], i64
+    L.qfs_set_option.argtypes, L.qfs_set_option.restype = [ctypes.c_char_p, i64], i32
+    L.qfs_get_option.argtypes, L.qfs_get_option.restype = [ctypes.c_char_p], i64
     L.qfs_last_error.argtypes, L.qfs_last_error.restype = [], ctypes.c_char_p
     L.qfs_shutdown.argtypes, L.qfs_shutdown.restype = [], None
     _lib = L
@@ -197,7 +200,8 @@ def height_plain(f, p, bound=10, workspace=None):
 
 
 # --------------------------------------------------------------------------- diagnostics
-STAGES = ("stage1", "plan", "deep_p3", "deep_p5", "deep_p7", "deep_p11")
+STAGES = ("stage1", "plan", "band_p3", "band_p5", "band_p7", "band_p11",
+          "deep_p3", "deep_p5", "deep_p7", "deep_p11")
 
 
 def profile(on):
@@ -207,12 +211,25 @@ def profile(on):
 
 def profile_collect():
     """(summed milliseconds per stage, number of calls) since the last collect."""
-    ms = (ctypes.c_double * 6)()
+    ms = (ctypes.c_double * len(STAGES))()
     calls = ctypes.c_int(0)
     _check(lib().qfs_profile_collect(ctypes.cast(ms, ctypes.c_void_p), ctypes.cast(ctypes.pointer(calls), ctypes.c_void_p)))
     return dict(zip(STAGES, list(ms))), calls.value
 
 
-def mfma_per_surface(p):
-    """v_mfma_i32_16x16x64_i8 instructions the Delta_1 product issues per surface at prime p."""
-    return int(lib().qfs_mfma_per_surface(int(p)))
+def mfma_per_surface(p, band=False):
+    """v_mfma_i32_16x16x64_i8 instructions the g~^p product issues per surface at prime p
+    (band: the capped chain qfs_height runs first; otherwise the full chain)."""
+    return int(lib().qfs_mfma_per_surface(int(p), 1 if band else 0))
+
+
+def set_option(name, value):
+    """Set a process-wide library option (see qfs_set_option in include/qfs.h)."""
+    _check(lib().qfs_set_option(name.encode(), int(value)))
+
+
+def get_option(name):
+    v = int(lib().qfs_get_option(name.encode()))
+    if v < 0:
+        raise QfsError(v, lib().qfs_last_error().decode())
+    return v

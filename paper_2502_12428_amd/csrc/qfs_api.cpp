@@ -4,6 +4,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -16,6 +17,9 @@ using namespace qfs;
 namespace {
 
 thread_local char g_err[512] = "";
+
+// process-wide options (qfs_set_option)
+std::atomic<bool> g_opt_height_band{true};
 
 int fail(int code, const char *fmt, ...)
 {
@@ -39,10 +43,17 @@ int device_cus()
 
 bool aligned(const void *p) { return ((uintptr_t)p & 255u) == 0; }
 
+// persistent workgroups of the g = f^(p-1) kernel: a few per compute unit
+int gpow_workgroups(int batch)
+{
+    const int n = 8 * device_cus();
+    return batch < n ? batch : n;
+}
+
 // ---- stage timing: hipEvents recorded on the caller's stream ----
 struct ProfRec {
-    hipEvent_t ev[10];
-    int stage[10];  // stage index of the interval ending at ev[i] (-1: none)
+    hipEvent_t ev[16];
+    int stage[16];  // stage index of the interval ending at ev[i] (-1: none)
     int n;
 };
 struct Prof {
@@ -75,7 +86,7 @@ struct ProfCall {
     }
     void mark(int stage)
     {
-        if (!on || r.n >= 10) return;
+        if (!on || r.n >= 16) return;
         hipEvent_t e;
         {
             std::lock_guard<std::mutex> lk(g_prof.m);
@@ -177,7 +188,8 @@ int qfs_delta1(int p, int batch, const uint8_t *f, uint8_t *g_out, uint8_t *delt
         s1.gq[i] = L.present[i] ? w + L.gq[i] : nullptr;
     }
     s1.present_mask = 1 << pi;
-    if ((e = launch_stage1(s1, p, stream)) != hipSuccess) return hip_fail(e, "stage1");
+    if ((e = launch_stage1(s1, stream)) != hipSuccess) return hip_fail(e, "stage1");
+    if ((e = launch_gpow(p, s1, gpow_workgroups(batch), stream)) != hipSuccess) return hip_fail(e, "g");
     if ((e = launch_plan(p, (uint32_t *)(w + L.plan[pi]), stream)) != hipSuccess) return hip_fail(e, "plan");
     DeepArgs da{};
     da.mode = MODE_DELTA;
@@ -190,8 +202,9 @@ int qfs_delta1(int p, int batch, const uint8_t *f, uint8_t *g_out, uint8_t *delt
     da.plan = (const uint32_t *)(w + L.plan[pi]);
     da.slots = w + L.slots;
     da.slot_bytes = L.slot_stride[pi];
+    da.zero_halo = 1;
     const int nslots = batch < L.nslots[pi] ? batch : L.nslots[pi];
-    if ((e = launch_deep(p, da, nslots, stream)) != hipSuccess) return hip_fail(e, "deep");
+    if ((e = launch_deep(p, false, da, nslots, stream)) != hipSuccess) return hip_fail(e, "deep");
     return QFS_OK;
 }
 
@@ -279,7 +292,10 @@ int qfs_height(int batch, const int32_t *p, const uint8_t *f, int bound, int max
         if (L.present[i]) mask |= 1 << i;
     }
     s1.present_mask = mask;
-    if ((e = launch_stage1(s1, max_p, stream)) != hipSuccess) return hip_fail(e, "stage1");
+    if ((e = launch_stage1(s1, stream)) != hipSuccess) return hip_fail(e, "stage1");
+    for (int i = 0; i < 4; ++i)
+        if (L.present[i] && (e = launch_gpow(kPrimes[i], s1, gpow_workgroups(batch), stream)) != hipSuccess)
+            return hip_fail(e, "g");
     prof.mark(0);
     for (int i = 0; i < 4; ++i) {
         if (!L.present[i]) continue;
@@ -292,13 +308,24 @@ int qfs_height(int batch, const int32_t *p, const uint8_t *f, int bound, int max
         da.heights = heights;
         da.counters = counters;
         da.queue = (const int32_t *)(w + L.queue[i]);
+        da.queue2 = (int32_t *)(w + L.queue2[i]);
         da.gq = w + L.gq[i];
         da.plan = (const uint32_t *)(w + L.plan[i]);
         da.slots = w + L.slots;
         da.slot_bytes = L.slot_stride[i];
         const int nslots = batch < L.nslots[i] ? batch : L.nslots[i];
-        if ((e = launch_deep(pp, da, nslots, stream)) != hipSuccess) return hip_fail(e, "deep");
+        // the capped chain decides h = 2 for every deep surface; the rest take
+        // the full chain in a second launch (balanced over all workgroups)
+        const bool band = g_opt_height_band.load() && bound >= 2;
+        if (band) {
+            da.zero_halo = 1;
+            if ((e = launch_deep(pp, true, da, nslots, stream)) != hipSuccess) return hip_fail(e, "deep band");
+        }
         prof.mark(2 + i);
+        da.from_q2 = band ? 1 : 0;
+        da.zero_halo = band ? 0 : 1;
+        if ((e = launch_deep(pp, false, da, nslots, stream)) != hipSuccess) return hip_fail(e, "deep");
+        prof.mark(6 + i);
     }
     return QFS_OK;
 }
@@ -310,11 +337,11 @@ int qfs_profile_enable(int on)
     return QFS_OK;
 }
 
-int qfs_profile_collect(double ms[6], int *calls)
+int qfs_profile_collect(double ms[QFS_PROFILE_STAGES], int *calls)
 {
     if (!ms || !calls) return fail(QFS_EINVAL, "qfs_profile_collect: null pointer");
     std::lock_guard<std::mutex> lk(g_prof.m);
-    for (int i = 0; i < 6; ++i) ms[i] = 0;
+    for (int i = 0; i < QFS_PROFILE_STAGES; ++i) ms[i] = 0;
     *calls = (int)g_prof.recs.size();
     int rc = QFS_OK;
     for (ProfRec &r : g_prof.recs) {
@@ -330,7 +357,28 @@ int qfs_profile_collect(double ms[6], int *calls)
     return rc;
 }
 
-int64_t qfs_mfma_per_surface(int p) { return supported(p) ? mfma_count(p) : -1; }
+int64_t qfs_mfma_per_surface(int p, int pass)
+{
+    if (!supported(p) || (pass != 0 && pass != 1)) return -1;
+    return mfma_count(p, pass == 1);
+}
+
+int qfs_set_option(const char *name, int64_t value)
+{
+    if (!name) return fail(QFS_EINVAL, "qfs_set_option: null name");
+    if (std::strcmp(name, "height_band") == 0) {
+        if (value != 0 && value != 1) return fail(QFS_EINVAL, "qfs_set_option: height_band must be 0 or 1");
+        g_opt_height_band.store(value != 0);
+        return QFS_OK;
+    }
+    return fail(QFS_EINVAL, "qfs_set_option: unknown option '%s'", name);
+}
+
+int64_t qfs_get_option(const char *name)
+{
+    if (name && std::strcmp(name, "height_band") == 0) return g_opt_height_band.load() ? 1 : 0;
+    return fail(QFS_EINVAL, "qfs_get_option: unknown option");
+}
 
 // ---------------------------------------------------------------------------
 size_t qfs_height_plain_workspace_bytes(int p) { return supported(p) ? plain_scratch_bytes(p) : 0; }

@@ -20,7 +20,7 @@
 namespace qfs {
 
 template <int P>
-__constant__ PlanTable<P> kPT = make_plan_table<P>();
+__constant__ PlanTable<P> kPT = kPlanTable<P>;
 
 // ---------------------------------------------------------------------------
 // reset
@@ -37,63 +37,88 @@ hipError_t launch_reset(int32_t *counters, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// stage 1
+// stage 1: Fedder's test for every surface, then g = f^(p-1) for the queued ones
 // ---------------------------------------------------------------------------
+template <int P>
+__constant__ CapTable<P> kCap = make_cap_table<P>();
+
+constexpr int S1_NT = 64;  // one wave per surface
+constexpr int S1_LDS = 48 + 35 * 4 + 2 * ((11 * 11 * 11 + 15) / 16 * 16);
+
+// Coefficient of (x1 x2 x3 x4)^(P-1) in f^(P-1) mod P (Fedder's criterion,
+// Section 2.2): the powers f^j are kept only on the monomials whose exponents
+// are all <= P-1 (a P^3 cube indexed by x1, x2, x3; x4 follows from the
+// degree), which determines that coefficient exactly.  One wave.
+template <int P>
+__device__ int fedder_coefficient(const uint8_t *f35, uint8_t *lds)
+{
+    constexpr int C3 = (P * P * P + 15) / 16 * 16;
+    uint32_t *taps = (uint32_t *)(lds + 48);
+    uint8_t *cur = lds + 48 + 35 * 4, *nxt = cur + C3;
+    const int lane = threadIdx.x;
+    const int nt = compact_taps(f35, taps);
+    for (int i = lane; i < kCap<P>.len[1]; i += S1_NT) {
+        const uint32_t m = kCap<P>.m[kCap<P>.off[1] + i];
+        const int x1 = m & 255, x2 = (m >> 8) & 255, x3 = (m >> 16) & 255, x4 = m >> 24;
+        cur[(x1 * P + x2) * P + x3] = f35[cns_rank(x2, x3, x4)];
+    }
+    __syncthreads();
+    for (int j = 1; j < P - 1; ++j) {
+        const int off = kCap<P>.off[j + 1], len = kCap<P>.len[j + 1];
+        for (int i = lane; i < len; i += S1_NT) {
+            const uint32_t m = kCap<P>.m[off + i];
+            const int x1 = m & 255, x2 = (m >> 8) & 255, x3 = (m >> 16) & 255, x4 = m >> 24;
+            int acc = 0;
+            for (int k = 0; k < nt; ++k) {
+                const uint32_t te = taps[k];
+                const int t1 = te & 255, t2 = (te >> 8) & 255, t3 = (te >> 16) & 255, t4 = 4 - t1 - t2 - t3;
+                if (x1 >= t1 && x2 >= t2 && x3 >= t3 && x4 >= t4)
+                    acc += (int)(te >> 24) * cur[((x1 - t1) * P + (x2 - t2)) * P + (x3 - t3)];
+            }
+            nxt[(x1 * P + x2) * P + x3] = (uint8_t)(acc % P);
+        }
+        __syncthreads();
+        uint8_t *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    return cur[((P - 1) * P + (P - 1)) * P + (P - 1)];
+}
+
 template <int P>
 __device__ void stage1_one(const Stage1Args &a, int surf, uint8_t *lds)
 {
-    using PR = Prime<P>;
-    constexpr int LG = PR::len_g;
-    constexpr int LGA = (LG + 15) / 16 * 16;
     uint8_t *f35 = lds;
-    int *flag = (int *)(lds + 48);
-    uint8_t *b0 = lds + 64, *b1 = b0 + LGA;
-    const int tid = threadIdx.x, pi = prime_index(P);
-    if (tid == 0) flag[0] = 0;
-    __syncthreads();
-    if (tid < 35) {
-        const int v = a.f[(size_t)surf * 35 + tid];
-        f35[tid] = (uint8_t)(v % P);
-        if (v >= P) atomicOr(flag, 1);
+    const int lane = threadIdx.x, pi = prime_index(P);
+    int v = 0;
+    if (lane < 35) {
+        v = a.f[(size_t)surf * 35 + lane];
+        f35[lane] = (uint8_t)(v % P);
     }
+    const bool bad = __ballot(v >= P) != 0;
     __syncthreads();
-    const bool bad = flag[0] != 0;
-    const uint8_t *g = fpow_lds<P>(f35, b0, b1);
-    const bool deep = g[PR::e_index] == 0;
     if (a.mode == MODE_HEIGHT) {
         if (bad) {
-            if (tid == 0) a.heights[surf] = -1; /* QFS_EINVAL */
+            if (lane == 0) a.heights[surf] = -1; /* QFS_EINVAL */
             return;
         }
-        if (!deep || a.bound < 2) {
-            if (tid == 0) a.heights[surf] = deep ? 0 : 1;
-            return;
+        const bool deep = fedder_coefficient<P>(f35, lds) == 0;
+        if (lane == 0) {
+            if (!deep || a.bound < 2)
+                a.heights[surf] = deep ? 0 : 1;
+            else
+                a.queue[pi][atomicAdd(&a.counters[CNT_COUNT + pi], 1)] = surf;
         }
-        __syncthreads();
-        if (tid == 0) flag[1] = atomicAdd(&a.counters[CNT_COUNT + pi], 1);
-        __syncthreads();
-        const int pos = flag[1];
-        if (tid == 0) a.queue[pi][pos] = surf;
-        uint8_t *dst = a.gq[pi] + (size_t)pos * LG;
-        for (int i = tid; i < LG; i += blockDim.x) dst[i] = g[i];
-    } else {
-        if (tid == 0) {
-            a.queue[pi][surf] = surf;
-            if (a.status) a.status[surf] = bad ? -1 : 0;
-            if (surf == 0) a.counters[CNT_COUNT + pi] = a.batch;
-        }
-        uint8_t *dst = a.gq[pi] + (size_t)surf * LG;
-        for (int i = tid; i < LG; i += blockDim.x) dst[i] = g[i];
-        if (a.g_out) {
-            uint8_t *go = a.g_out + (size_t)surf * LG;
-            for (int i = tid; i < LG; i += blockDim.x) go[i] = g[i];
-        }
+    } else if (lane == 0) {
+        a.queue[pi][surf] = surf;
+        if (a.status) a.status[surf] = bad ? -1 : 0;
+        if (surf == 0) a.counters[CNT_COUNT + pi] = a.batch;
     }
 }
 
-__global__ __launch_bounds__(256) void k_stage1(Stage1Args a)
+__global__ __launch_bounds__(S1_NT) void k_stage1(Stage1Args a)
 {
-    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ __align__(16) uint8_t lds[S1_LDS];
     const int surf = blockIdx.x;
     const int p = a.fixed_p > 0 ? a.fixed_p : a.p[surf];
     const int pi = prime_index(p);
@@ -112,16 +137,49 @@ __global__ __launch_bounds__(256) void k_stage1(Stage1Args a)
     }
 }
 
-size_t dyn_lds_stage1(int max_p)
-{
-    const int64_t lg = len_g_of(max_p);
-    return 64 + 2 * (size_t)((lg + 15) / 16 * 16);
-}
-
-hipError_t launch_stage1(const Stage1Args &a, int max_p, hipStream_t s)
+hipError_t launch_stage1(const Stage1Args &a, hipStream_t s)
 {
     if (a.batch <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_stage1, dim3(a.batch), dim3(256), dyn_lds_stage1(max_p), s, a);
+    hipLaunchKernelGGL(k_stage1, dim3(a.batch), dim3(S1_NT), 0, s, a);
+    return hipGetLastError();
+}
+
+// g = f^(P-1) mod P for the queued surfaces of prime P (persistent: workgroup
+// b takes queue positions b, b + grid, ...), into gq (and g_out in MODE_DELTA).
+template <int P>
+__global__ __launch_bounds__(256) void k_gpow(Stage1Args a)
+{
+    constexpr int LG = Prime<P>::len_g, LGA = (LG + 15) / 16 * 16;
+    __shared__ __align__(16) uint8_t f35[64], b0[LGA], b1[LGA];
+    __shared__ uint32_t taps[35];
+    __shared__ int ntap;
+    const int tid = threadIdx.x, pi = prime_index(P);
+    const int count = a.counters[CNT_COUNT + pi];
+    for (int pos = blockIdx.x; pos < count; pos += gridDim.x) {
+        const int surf = a.queue[pi][pos];
+        if (tid < 35) f35[tid] = (uint8_t)(a.f[(size_t)surf * 35 + tid] % P);
+        __syncthreads();
+        const uint8_t *g = fpow_lds<P>(f35, b0, b1, taps, &ntap);
+        uint8_t *dst = a.gq[pi] + (size_t)pos * LG;
+        for (int i = tid; i < LG; i += blockDim.x) dst[i] = g[i];
+        if (a.mode == MODE_DELTA && a.g_out) {
+            uint8_t *go = a.g_out + (size_t)surf * LG;
+            for (int i = tid; i < LG; i += blockDim.x) go[i] = g[i];
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_gpow(int p, const Stage1Args &a, int nwg, hipStream_t s)
+{
+    if (a.batch <= 0 || nwg <= 0) return hipSuccess;
+    switch (p) {
+    case 3: hipLaunchKernelGGL(k_gpow<3>, dim3(nwg), dim3(256), 0, s, a); break;
+    case 5: hipLaunchKernelGGL(k_gpow<5>, dim3(nwg), dim3(256), 0, s, a); break;
+    case 7: hipLaunchKernelGGL(k_gpow<7>, dim3(nwg), dim3(256), 0, s, a); break;
+    case 11: hipLaunchKernelGGL(k_gpow<11>, dim3(nwg), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -133,20 +191,37 @@ __global__ __launch_bounds__(256) void k_plan(uint32_t *plan)
 {
     using X = GeoX<P>;
     constexpr int d = 4 * (P - 1);
-    const bool is_base = blockIdx.x < P;
-    const int k = is_base ? blockIdx.x : blockIdx.x - P;
-    if (is_base ? (k < 1) : (k > P - 2)) return;
-    const int m = is_base ? (k + 1) * d : (k + 2) * d + 4;
-    uint32_t *out = plan + (is_base ? kPT<P>.boff[k] : kPT<P>.foff[k]);
+    const int kind = blockIdx.x / P, k = blockIdx.x % P;  // 0 base, 1 shell, 2 band
+    if (kind == 1 ? (k > P - 2) : (k < 1)) return;
+    const int m = kind == 1 ? (k + 2) * d + 4 : (k + 1) * d;
+    uint32_t *out = plan + (kind == 0 ? kPT<P>.boff[k] : kind == 1 ? kPT<P>.foff[k] : kPT<P>.noff[k]);
     __shared__ int cnt[256];
-    const int c1 = threadIdx.x;
-    const int step = is_base ? 2 : 1;
-    const bool mine_slab = (c1 % step == 0) && T1 * c1 <= m && (is_base || c1 <= X::C1);
+    const int tid = threadIdx.x;
+    if (kind != 1) {
+        // blocks of base units, a contiguous range of block indices per thread
+        const bool band = kind == 2;
+        auto keep = [&](uint32_t t) { return !band || band_tile_packed<P>(m, t); };
+        const PlanBlocks nb = plan_blocks(m);
+        const int nblk = nb.n1 * nb.n2 * nb.n3;
+        const int per = (nblk + 255) / 256;
+        const int b0 = min(nblk, tid * per), b1 = min(nblk, b0 + per);
+        int mine = 0;
+        for (int b = b0; b < b1; ++b) mine += plan_block_emit(m, b, keep, [](int, uint32_t) {});
+        cnt[tid] = mine;
+        __syncthreads();
+        int off = 0;
+        for (int i = 0; i < tid; ++i) off += cnt[i];
+        for (int b = b0; b < b1; ++b) off += plan_block_emit(m, b, keep, [&](int i, uint32_t t) { out[off + i] = t; });
+        return;
+    }
+    // shell lists: one slab c1 per thread, any order
+    const int c1 = tid;
+    const bool mine_slab = T1 * c1 <= m && c1 <= X::C1;
     int mine = 0;
     if (mine_slab)
-        for (int c2 = 0; T1 * c1 + T2 * c2 <= m && (is_base || c2 <= X::C2); c2 += step) {
+        for (int c2 = 0; T1 * c1 + T2 * c2 <= m && c2 <= X::C2; ++c2) {
             int top = (m - T1 * c1 - T2 * c2) / T3;
-            if (!is_base && top > X::C3 - 1) top = X::C3 - 1;
+            if (top > X::C3 - 1) top = X::C3 - 1;
             mine += top + 1;
         }
     cnt[c1] = mine;
@@ -154,9 +229,9 @@ __global__ __launch_bounds__(256) void k_plan(uint32_t *plan)
     if (mine_slab) {
         int off = 0;
         for (int i = 0; i < c1; ++i) off += cnt[i];
-        for (int c2 = 0; T1 * c1 + T2 * c2 <= m && (is_base || c2 <= X::C2); c2 += step) {
+        for (int c2 = 0; T1 * c1 + T2 * c2 <= m && c2 <= X::C2; ++c2) {
             int top = (m - T1 * c1 - T2 * c2) / T3;
-            if (!is_base && top > X::C3 - 1) top = X::C3 - 1;
+            if (top > X::C3 - 1) top = X::C3 - 1;
             for (int c3 = 0; c3 <= top; ++c3) out[off++] = pack3(c1, c2, c3);
         }
     }
@@ -165,10 +240,10 @@ __global__ __launch_bounds__(256) void k_plan(uint32_t *plan)
 hipError_t launch_plan(int p, uint32_t *plan, hipStream_t s)
 {
     switch (p) {
-    case 3: hipLaunchKernelGGL(k_plan<3>, dim3(6), dim3(256), 0, s, plan); break;
-    case 5: hipLaunchKernelGGL(k_plan<5>, dim3(10), dim3(256), 0, s, plan); break;
-    case 7: hipLaunchKernelGGL(k_plan<7>, dim3(14), dim3(256), 0, s, plan); break;
-    case 11: hipLaunchKernelGGL(k_plan<11>, dim3(22), dim3(256), 0, s, plan); break;
+    case 3: hipLaunchKernelGGL(k_plan<3>, dim3(9), dim3(256), 0, s, plan); break;
+    case 5: hipLaunchKernelGGL(k_plan<5>, dim3(15), dim3(256), 0, s, plan); break;
+    case 7: hipLaunchKernelGGL(k_plan<7>, dim3(21), dim3(256), 0, s, plan); break;
+    case 11: hipLaunchKernelGGL(k_plan<11>, dim3(33), dim3(256), 0, s, plan); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -177,7 +252,15 @@ hipError_t launch_plan(int p, uint32_t *plan, hipStream_t s)
 // ---------------------------------------------------------------------------
 // deep kernel
 // ---------------------------------------------------------------------------
-constexpr int DEEP_NT = 512, DEEP_NW = DEEP_NT / 64, DEEP_NB = 4;
+// Threads per deep workgroup (one workgroup per CU: the W blocks fill most of
+// the LDS), and how many list entries ahead the input fragments are loaded.
+#ifndef QFS_DEEP_NT
+#define QFS_DEEP_NT 512
+#endif
+#ifndef QFS_DEEP_PF
+#define QFS_DEEP_PF 3
+#endif
+constexpr int DEEP_NT = QFS_DEEP_NT, DEEP_NW = DEEP_NT / 64, DEEP_NB = 4, DEEP_PF = QFS_DEEP_PF;
 
 template <int P>
 __constant__ DeltaTableX<P> kDX = make_delta_table_x<P>();
@@ -195,8 +278,9 @@ struct DeepLds {
     static constexpr int off_toff = off_aperm + APA;
     static constexpr int off_widx = off_toff + 4 * (X::NVXP + 4);
     static constexpr int off_qbox = off_widx + 8 * (X::NVXP + 4);
-    static constexpr int off_qlist = off_qbox + 8 * X::NQX;
-    static constexpr int off_red = off_qlist + ((2 * (X::NQX + 1) * (DEEP_NT / 64) + 15) / 16 * 16);
+    static constexpr int off_qlist = off_qbox + 16 * X::NQX;
+    static constexpr int QSTRIDE = X::NQX + DEEP_PF;  // a wave's needed-quad list, padded
+    static constexpr int off_red = off_qlist + ((2 * QSTRIDE * (DEEP_NT / 64) + 15) / 16 * 16);
     static constexpr int bytes = off_red + 4 * 64;
 };
 
@@ -253,19 +337,22 @@ __device__ void init_a1(const uint8_t *g, const uint32_t *list, int ntiles, uint
     }
 }
 
-// Zero the tiles of a shell list with w(c) > n: the next product reads them as zeros.
+// Zero the tiles of a shell list with w(c) > n: the next product reads them as
+// zeros.  The capped chain reads only tiles whose coordinates are all <= cap.
 template <int P>
-__device__ void zero_shell(const uint32_t *list, int ntiles, int n, uint8_t *A)
+__device__ void zero_shell(const uint32_t *list, int ntiles, int n, int cap, uint8_t *A)
 {
     for (int i = threadIdx.x; i < ntiles; i += blockDim.x) {
         const uint32_t t = list[i];
         const int c1 = unp0(t), c2 = unp1(t), c3 = unp2(t);
-        if (T1 * c1 + T2 * c2 + T3 * c3 > n) gstore16(A + box_tile<P>(c1, c2, c3) * 16, v4u{0, 0, 0, 0});
+        if (T1 * c1 + T2 * c2 + T3 * c3 > n && T1 * c1 <= cap && T2 * c2 <= cap && T3 * c3 <= cap)
+            gstore16(A + box_tile<P>(c1, c2, c3) * 16, v4u{0, 0, 0, 0});
     }
 }
 
 struct EpiCtx {
     int mode;
+    bool win;         // capped chain: only the window p^2-1-d <= x_i <= p^2-1 is formed and checked
     uint8_t *dout;    // MODE_DELTA: Delta in CNS order for this surface
     const uint8_t *g; // LDS
     int *err;         // LDS flag
@@ -274,7 +361,7 @@ struct EpiCtx {
 // Delta_1 epilogue for the four positions s = 4 kg + v of output tile c:
 // D = (g~^p - sum_J b_J^p x^(pJ)) / p mod p (Algorithm 1, lines 3-5).
 // Returns the four values packed in a word (byte v for position 4 kg + v;
-// positions beyond degree D give 0).  MODE_DELTA also scatters them to the
+// positions beyond degree D, and in the capped chain outside the window, give 0).  MODE_DELTA also scatters them to the
 // caller's array in CNS order.
 template <int P>
 __device__ __attribute__((always_inline)) inline unsigned epilogue(int c1, int c2, int c3, int kg, v4i acc,
@@ -289,6 +376,10 @@ __device__ __attribute__((always_inline)) inline unsigned epilogue(int c1, int c
         const int x3 = T3 * c3 + v;
         const int x4 = D - x1 - x2 - x3;
         if (x4 < 0) continue;
+        if (ec.win) {
+            constexpr int E = P2 - 1, LO = E - 4 * (P - 1);
+            if (x1 < LO || x1 > E || x2 < LO || x2 > E || x3 < LO || x3 > E || x4 < LO || x4 > E) continue;
+        }
         int val = acc[v] % P2;
         if (j12 && x3 % P == 0) {
             const int bj = ec.g[cns_rank(x2 / P, x3 / P, x4 / P)];
@@ -309,7 +400,7 @@ __device__ __attribute__((always_inline)) inline unsigned epilogue(int c1, int c
 // fragment per shift (blocks W_{delta + Delta_s}), then issues up to
 // 4 * NB products D[s][tile] += W[s][(delta, s')] * A[(delta, s')][tile].
 template <int P>
-__device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *list, int nbase, int gs, int nk, const uint8_t *W,
+__device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *list, int nbase, int gs, int nk, int cap, const uint8_t *W,
                          const uint8_t *__restrict__ Ain, uint8_t *Aout, bool last, const int *toff_l,
                          const uint32_t *widx_l, const uint32_t *qbox_l, uint16_t *qlist, const EpiCtx &ec)
 {
@@ -320,7 +411,7 @@ __device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *l
 
     int64_t base[NB];
     bool ok[NB], gex[NB];
-    int gmax1[NB], gmax2[NB], gmax3[NB], gwmin[NB];
+    int gmax1[NB], gmax2[NB], gmax3[NB], gwmin[NB], gmin1[NB], gmin2[NB], gmin3[NB], gwmax[NB];
     uint32_t tpk[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -336,6 +427,10 @@ __device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *l
         gmax2[b] = uniform(wave_max(c2));
         gmax3[b] = uniform(wave_max(c3));
         gwmin[b] = uniform(wave_min(T1 * c1 + T2 * c2 + T3 * c3));
+        gmin1[b] = uniform(wave_min(c1));
+        gmin2[b] = uniform(wave_min(c2));
+        gmin3[b] = uniform(wave_min(c3));
+        gwmax[b] = uniform(wave_max(T1 * c1 + T2 * c2 + T3 * c3));
     }
     v4i acc[4][NB];
 #pragma unroll
@@ -349,7 +444,7 @@ __device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *l
     // every shift is multiplied: tiles outside A_k read the zero halo or the
     // zeroed shell and the zero W block adds nothing, so the products stay exact
     // and the loop has no branches around the matrix instructions.
-    int smax1 = 0, smax2 = 0, smax3 = 0, swmin = 1 << 30;
+    int smax1 = 0, smax2 = 0, smax3 = 0, swmin = 1 << 30, smin1 = 1 << 30, smin2 = 1 << 30, smin3 = 1 << 30, swmax = 0;
 #pragma unroll
     for (int b = 0; b < NB; ++b)
         if (gex[b]) {
@@ -357,26 +452,30 @@ __device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *l
             smax2 = max(smax2, gmax2[b]);
             smax3 = max(smax3, gmax3[b]);
             swmin = min(swmin, gwmin[b]);
+            smin1 = min(smin1, gmin1[b]);
+            smin2 = min(smin2, gmin2[b]);
+            smin3 = min(smin3, gmin3[b]);
+            swmax = max(swmax, gwmax[b]);
         }
     // the quads this set needs, in order, into the wave's list in LDS
     int nq = 0;
     for (int q0 = 0; q0 < X::NQX; q0 += 64) {
         const int q = q0 + lane;
         bool nd = false;
-        if (q < X::NQX) {
-            const uint32_t qmin = qbox_l[2 * q];
-            nd = smax1 >= (int)unp0(qmin) - 1 && smax2 >= (int)unp1(qmin) - 1 && smax3 >= (int)unp2(qmin) &&
-                 swmin - (int)qbox_l[2 * q + 1] <= nk;
-        }
+        if (q < X::NQX)
+            nd = quad_needed(smax1, smax2, smax3, swmin, smin1, smin2, smin3, swmax, nk, cap, qbox_l[4 * q],
+                             (int)qbox_l[4 * q + 1], qbox_l[4 * q + 2], (int)qbox_l[4 * q + 3]);
         const uint64_t m = __ballot(nd);
         if (nd) qlist[nq + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)q;
         nq += __popcll(m);
     }
     nq = uniform(nq);
-    // pad to an even count with the null quad (index NQX: offset 0, zero W blocks)
-    if (nq & 1) {
-        if (lane == 0) qlist[nq] = (uint16_t)X::NQX;
-        ++nq;
+    // pad to a multiple of the prefetch depth with the null quad (index NQX:
+    // offset 0, zero W blocks)
+    {
+        const int npad = (DEEP_PF - nq % DEEP_PF) % DEEP_PF;
+        if (lane < npad) qlist[nq + lane] = (uint16_t)X::NQX;
+        nq += npad;
     }
 
     // byte offsets of the tiles inside the box fit in 32 bits
@@ -407,22 +506,22 @@ __device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *l
                 acc[s][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(wf_[s], BF[b], acc[s][b], 0, 0, 0);       \
     } while (0)
 
-    // two fragment sets alternate; each is refilled two entries ahead of its use
+    // DEEP_PF fragment sets rotate; each is refilled DEEP_PF entries ahead of its use
     if (nq > 0) {
-        v4i bfa[NB], bfb[NB];
-        QFS_LOAD_B(bfa, 0);
-        __builtin_amdgcn_sched_barrier(0);
-        QFS_LOAD_B(bfb, 1);
-        __builtin_amdgcn_sched_barrier(0);
-        for (int i = 0; i < nq; i += 2) {
-            QFS_PRODUCTS(bfa, i);
+        v4i bf[DEEP_PF][NB];
+#pragma unroll
+        for (int j = 0; j < DEEP_PF; ++j) {
+            QFS_LOAD_B(bf[j], j);
             __builtin_amdgcn_sched_barrier(0);
-            QFS_LOAD_B(bfa, i + 2);
-            __builtin_amdgcn_sched_barrier(0);
-            QFS_PRODUCTS(bfb, i + 1);
-            __builtin_amdgcn_sched_barrier(0);
-            QFS_LOAD_B(bfb, i + 3);
-            __builtin_amdgcn_sched_barrier(0);
+        }
+        for (int i = 0; i < nq; i += DEEP_PF) {
+#pragma unroll
+            for (int j = 0; j < DEEP_PF; ++j) {
+                QFS_PRODUCTS(bf[j], i + j);
+                __builtin_amdgcn_sched_barrier(0);
+                QFS_LOAD_B(bf[j], i + j + DEEP_PF);
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
     }
 #undef QFS_LOAD_B
@@ -439,7 +538,7 @@ __device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *l
             unsigned packed = 0;
             if (!last) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) packed |= (unsigned)(acc[s][b][v] % P2) << (8 * v);
+                for (int v = 0; v < 4; ++v) packed |= ((unsigned)(acc[s][b][v] % P2) & 255u) << (8 * v);
             } else {
                 packed = epilogue<P>(c1 + d1, c2 + d2, c3, kg, acc[s][b], ec);
             }
@@ -488,14 +587,48 @@ __device__ void box_to_theta(const uint8_t *dbox, const uint32_t *list, int nbas
     }
 }
 
+// The chain A_{k+1} = A_k * g~, k = 1..P-1, into the two tile boxes, from the
+// W blocks and g already in place: in full, or (band) only the super-tiles
+// that the height-2 test depends on, ending in the window of Delta it reads.
 template <int P>
+__device__ __attribute__((always_inline)) inline void run_chain(bool band, const uint32_t *plan, const uint8_t *g_l,
+                                                               const uint8_t *W, uint8_t *buf0, uint8_t *buf1,
+                                                               const int *toff_l, const uint32_t *widx_l,
+                                                               const uint32_t *qbox_l, uint16_t *qlist_w, EpiCtx ec)
+{
+    constexpr int d = 4 * (P - 1);
+    const int wave = uniform(threadIdx.x >> 6);
+    const int cap = band ? P * P - 1 : CAP_NONE;
+    init_a1<P>(g_l, plan + kPT<P>.foff[0], (int)kPT<P>.flen[0], buf0);
+    __syncthreads();
+    for (int k = 1; k < P; ++k) {
+        const uint8_t *Ain = (k & 1) ? buf0 : buf1;
+        uint8_t *Aout = (k & 1) ? buf1 : buf0;
+        const int nbase = (int)(band ? kPT<P>.nlen[k] : kPT<P>.blen[k]);
+        const uint32_t *list = plan + (band ? kPT<P>.noff[k] : kPT<P>.boff[k]);
+        const int nsets = ((nbase + 15) / 16 + DEEP_NB - 1) / DEEP_NB;
+        const bool last = (k == P - 1);
+        ec.win = band && last;
+        for (int gs = wave; gs < nsets; gs += DEEP_NW)
+            mfma_set<P>(list, nbase, gs, k * d, cap, W, Ain, Aout, last, toff_l, widx_l, qbox_l, qlist_w, ec);
+        if (!last) zero_shell<P>(plan + kPT<P>.foff[k], (int)kPT<P>.flen[k], (k + 1) * d, cap, Aout);
+        __syncthreads();
+    }
+}
+
+// Persistent deep kernel: each workgroup pops surfaces (queue positions) and
+// owns one slot (two tile boxes and the Cartier-split Delta).
+//  BAND (MODE_HEIGHT): the capped chain and the first test; h = 2 (or, for
+//    bound 2, infinity) is written at once, other surfaces go to the second queue.
+//  !BAND: the full chain g~^p with the Delta_1 epilogue, then (MODE_HEIGHT)
+//    Algorithm 3's theta loop, or (MODE_DELTA) Delta written out in CNS order.
+template <int P, bool BAND>
 __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
 {
     using PR = Prime<P>;
     using X = GeoX<P>;
     using L = DeepLds<P>;
     constexpr int LG = PR::len_g;
-    constexpr int d = PR::d;
     extern __shared__ __align__(16) uint8_t lds[];
     uint8_t *g_l = lds + L::off_g;
     uint8_t *aperm = lds + L::off_aperm;
@@ -515,7 +648,9 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
     uint8_t *dl = bufs + 2 * align256(X::BOX_BYTES);
     uint8_t *W = w_in_lds<P>() ? lds + L::off_w : wg;
 
-    const int count = a.counters[CNT_COUNT + pi];
+    const bool q2 = !BAND && a.from_q2;
+    const int count = a.counters[(q2 ? CNT_Q2 : CNT_COUNT) + pi];
+    const int popc = (q2 ? CNT_POP2 : CNT_POP) + pi;
     if ((int)blockIdx.x >= count) return;  // more workgroups than surfaces: nothing to do
     for (int i = tid; i < X::NVXP; i += DEEP_NT) {
         toff_l[i] = kDX<P>.toff[i];
@@ -527,55 +662,66 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
         widx_l[2 * (X::NVXP + tid)] = widx_l[2 * (X::NVXP + tid) + 1] = (uint32_t)X::NV | ((uint32_t)X::NV << 16);
     }
     for (int i = tid; i < X::NQX; i += DEEP_NT) {
-        qbox_l[2 * i] = kDX<P>.qmin[i];
-        qbox_l[2 * i + 1] = (uint32_t)kDX<P>.qwmax[i];
+        qbox_l[4 * i] = kDX<P>.qmin[i];
+        qbox_l[4 * i + 1] = (uint32_t)kDX<P>.qwmax[i];
+        qbox_l[4 * i + 2] = kDX<P>.qmax[i];
+        qbox_l[4 * i + 3] = (uint32_t)kDX<P>.qwmin[i];
     }
     // the halo (tiles with a negative coordinate) of both boxes is read as zero and never written
-    for (int64_t t = tid; t < X::BOX_TILES; t += DEEP_NT) {
-        const int i3 = (int)(t % X::B3);
-        const int64_t r = t / X::B3;
-        const int i2 = (int)(r % X::B2), i1 = (int)(r / X::B2);
-        if (i1 < X::H1 || i2 < X::H2 || i3 < X::H3) {
-            gstore16(buf[0] + t * 16, v4u{0, 0, 0, 0});
-            gstore16(buf[1] + t * 16, v4u{0, 0, 0, 0});
+    if (a.zero_halo)
+        for (int64_t t = tid; t < X::BOX_TILES; t += DEEP_NT) {
+            const int i3 = (int)(t % X::B3);
+            const int64_t r = t / X::B3;
+            const int i2 = (int)(r % X::B2), i1 = (int)(r / X::B2);
+            if (i1 < X::H1 || i2 < X::H2 || i3 < X::H3) {
+                gstore16(buf[0] + t * 16, v4u{0, 0, 0, 0});
+                gstore16(buf[1] + t * 16, v4u{0, 0, 0, 0});
+            }
         }
-    }
 
     for (;;) {
         __syncthreads();
         if (tid == 0) {
-            s_pos = atomicAdd(&a.counters[CNT_POP + pi], 1);
+            s_pos = atomicAdd(&a.counters[popc], 1);
             s_err = 0;
         }
         __syncthreads();
         const int pos = s_pos;
         if (pos >= count) break;
-        const int surf = a.queue[pos];
-        for (int i = tid; i < LG; i += DEEP_NT) g_l[i] = a.gq[(size_t)pos * LG + i];
+        const int qpos = q2 ? a.queue2[pos] : pos;  // position in the first queue
+        const int surf = a.queue[qpos];
+        for (int i = tid; i < LG; i += DEEP_NT) g_l[i] = a.gq[(size_t)qpos * LG + i];
         __syncthreads();
         build_w<P>(g_l, W);
-        init_a1<P>(g_l, a.plan + kPT<P>.foff[0], (int)kPT<P>.flen[0], buf[0]);
         __syncthreads();
 
         EpiCtx ec;
         ec.mode = a.mode;
+        ec.win = false;
         ec.dout = a.delta_out ? a.delta_out + (size_t)surf * PR::len_D : nullptr;
         ec.g = g_l;
         ec.err = &s_err;
-        for (int k = 1; k < P; ++k) {
-            const uint8_t *Ain = buf[(k - 1) & 1];
-            uint8_t *Aout = buf[k & 1];
-            const int nbase = (int)kPT<P>.blen[k];
-            const int nsets = ((nbase + 15) / 16 + DEEP_NB - 1) / DEEP_NB;
-            const bool last = (k == P - 1);
-            const uint32_t *list = a.plan + kPT<P>.boff[k];
-            for (int gs = wave; gs < nsets; gs += DEEP_NW)
-                mfma_set<P>(list, nbase, gs, k * d, W, Ain, Aout, last, toff_l, widx_l, qbox_l, qlist_l + wave * (X::NQX + 1), ec);
-            if (!last) zero_shell<P>(a.plan + kPT<P>.foff[k], (int)kPT<P>.flen[k], (k + 1) * d, Aout);
-            __syncthreads();
-        }
+        uint16_t *qlist_w = qlist_l + wave * L::QSTRIDE;
+        run_chain<P>(BAND, a.plan, g_l, W, buf[0], buf[1], toff_l, widx_l, qbox_l, qlist_w, ec);
         const bool err = s_err != 0;
 
+        if (BAND) {
+            // h = 2 needs only the window of Delta the first test reads
+            int hv = -1;
+            if (err)
+                hv = -5; /* QFS_EARITH */
+            else if (theta_test_box<P>(buf[(P - 1) & 1], g_l, red) != 0)
+                hv = 2;
+            else if (a.bound == 2)
+                hv = 0;
+            if (tid == 0) {
+                if (hv != -1)
+                    a.heights[surf] = hv;
+                else
+                    a.queue2[atomicAdd(&a.counters[CNT_Q2 + pi], 1)] = qpos;
+            }
+            continue;
+        }
         if (a.mode == MODE_DELTA) {
             if (tid == 0 && err && a.status) a.status[surf] = -5; /* QFS_EARITH */
             continue;
@@ -585,15 +731,18 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
             continue;
         }
         // Algorithm 3's loop: the test reads c(theta(a)) only; theta(a) in full
-        // is needed only when the surface goes on to the next h.
+        // is needed only when the surface goes on to the next h.  Surfaces from
+        // the second queue are known to fail the first test.
         const uint8_t *dbox = buf[(P - 1) & 1];
         int h = 0;
         bool split = false;
         for (int hh = 2; hh <= a.bound; ++hh) {
-            const int t = theta_test_box<P>(dbox, g_l, red);
-            if (t != 0) {
-                h = hh;
-                break;
+            if (hh > 2 || !q2) {
+                const int t = theta_test_box<P>(dbox, g_l, red);
+                if (t != 0) {
+                    h = hh;
+                    break;
+                }
             }
             if (hh == a.bound) break;
             if (!split) {
@@ -609,24 +758,30 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
     }
 }
 
-template <int P>
-static hipError_t launch_deep_p(const DeepArgs &a, int nslots, hipStream_t s)
+template <int P, bool BAND>
+static hipError_t launch_deep_pb(const DeepArgs &a, int nslots, hipStream_t s)
 {
     const size_t lds = DeepLds<P>::bytes;
     static const hipError_t attr =
-        hipFuncSetAttribute((const void *)k_deep<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipFuncSetAttribute((const void *)k_deep<P, BAND>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(k_deep<P>, dim3(nslots), dim3(DEEP_NT), lds, s, a);
+    hipLaunchKernelGGL((k_deep<P, BAND>), dim3(nslots), dim3(DEEP_NT), lds, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_deep(int p, const DeepArgs &a, int nslots, hipStream_t s)
+template <int P>
+static hipError_t launch_deep_p(bool band, const DeepArgs &a, int nslots, hipStream_t s)
+{
+    return band ? launch_deep_pb<P, true>(a, nslots, s) : launch_deep_pb<P, false>(a, nslots, s);
+}
+
+hipError_t launch_deep(int p, bool band, const DeepArgs &a, int nslots, hipStream_t s)
 {
     switch (p) {
-    case 3: return launch_deep_p<3>(a, nslots, s);
-    case 5: return launch_deep_p<5>(a, nslots, s);
-    case 7: return launch_deep_p<7>(a, nslots, s);
-    case 11: return launch_deep_p<11>(a, nslots, s);
+    case 3: return launch_deep_p<3>(band, a, nslots, s);
+    case 5: return launch_deep_p<5>(band, a, nslots, s);
+    case 7: return launch_deep_p<7>(band, a, nslots, s);
+    case 11: return launch_deep_p<11>(band, a, nslots, s);
     }
     return hipErrorInvalidValue;
 }
@@ -636,54 +791,61 @@ hipError_t launch_deep(int p, const DeepArgs &a, int nslots, hipStream_t s)
 // only on the geometry, so this replays them.
 // ---------------------------------------------------------------------------
 template <int P>
-static int64_t mfma_count_p()
+static int64_t mfma_count_p(bool band)
 {
     using X = GeoX<P>;
-    constexpr int d = X::d;
+    constexpr int d = X::d, E = P * P - 1;
     static const DeltaTableX<P> DX = make_delta_table_x<P>();
     int64_t total = 0;
     for (int k = 1; k < P; ++k) {
-        const int n = (k + 1) * d, nk = k * d;
-        std::vector<uint32_t> tiles;
-        for (int c1 = 0; T1 * c1 <= n; c1 += 2)
-            for (int c2 = 0; T1 * c1 + T2 * c2 <= n; c2 += 2)
-                for (int c3 = 0; T1 * c1 + T2 * c2 + T3 * c3 <= n; ++c3) tiles.push_back(pack3(c1, c2, c3));
+        const int n = (k + 1) * d, nk = k * d, cap = band ? E : (1 << 20);
+        std::vector<uint32_t> tiles;  // the list in k_plan's order
+        const PlanBlocks nb = plan_blocks(n);
+        for (int b = 0; b < nb.n1 * nb.n2 * nb.n3; ++b)
+            plan_block_emit(n, b, [&](uint32_t t) { return !band || band_tile_packed<P>(n, t); },
+                            [&](int, uint32_t t) { tiles.push_back(t); });
         const int nt = (int)tiles.size();
+        if (nt != (band ? kPlanTable<P>.nlen[k] : kPlanTable<P>.blen[k])) return -1;  // list lengths disagree
         const int ngroups = (nt + 15) / 16;
         for (int gs = 0; gs * DEEP_NB < ngroups; ++gs) {
-            int m1 = 0, m2 = 0, m3 = 0, wmin = 1 << 30;
+            int m1 = 0, m2 = 0, m3 = 0, wmin = 1 << 30, l1 = 1 << 30, l2 = 1 << 30, l3 = 1 << 30, wmax = 0;
             for (int g = gs * DEEP_NB * 16; g < std::min(nt, (gs + 1) * DEEP_NB * 16); ++g) {
                 const uint32_t t = tiles[g];
                 m1 = std::max(m1, unp0(t));
                 m2 = std::max(m2, unp1(t));
                 m3 = std::max(m3, unp2(t));
+                l1 = std::min(l1, unp0(t));
+                l2 = std::min(l2, unp1(t));
+                l3 = std::min(l3, unp2(t));
                 wmin = std::min(wmin, T1 * unp0(t) + T2 * unp1(t) + T3 * unp2(t));
+                wmax = std::max(wmax, T1 * unp0(t) + T2 * unp1(t) + T3 * unp2(t));
             }
-            for (int q = 0; q < X::NQX; ++q) {
-                const uint32_t qm = DX.qmin[q];
-                if (m1 >= (int)unp0(qm) - 1 && m2 >= (int)unp1(qm) - 1 && m3 >= (int)unp2(qm) &&
-                    wmin - DX.qwmax[q] <= nk)
-                    total += 4 * DEEP_NB;
-            }
+            int nq = 0;
+            for (int q = 0; q < X::NQX; ++q)
+                nq += quad_needed(m1, m2, m3, wmin, l1, l2, l3, wmax, nk, cap, DX.qmin[q], DX.qwmax[q], DX.qmax[q],
+                                  DX.qwmin[q]);
+            nq += (DEEP_PF - nq % DEEP_PF) % DEEP_PF;  // null-quad padding
+            total += (int64_t)nq * 4 * DEEP_NB;
         }
     }
     return total;
 }
 
-int64_t mfma_count(int p)
+int64_t mfma_count(int p, bool band)
 {
-    static int64_t cache[4] = {-1, -1, -1, -1};
+    static int64_t cache[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};
     const int pi = prime_index(p);
     if (pi < 0) return -1;
-    if (cache[pi] < 0) {
+    int64_t &c = cache[band ? 1 : 0][pi];
+    if (c == -1) {
         switch (p) {
-        case 3: cache[pi] = mfma_count_p<3>(); break;
-        case 5: cache[pi] = mfma_count_p<5>(); break;
-        case 7: cache[pi] = mfma_count_p<7>(); break;
-        case 11: cache[pi] = mfma_count_p<11>(); break;
+        case 3: c = mfma_count_p<3>(band); break;
+        case 5: c = mfma_count_p<5>(band); break;
+        case 7: c = mfma_count_p<7>(band); break;
+        case 11: c = mfma_count_p<11>(band); break;
         }
     }
-    return cache[pi];
+    return c;
 }
 
 // ---------------------------------------------------------------------------
@@ -733,6 +895,8 @@ BatchLayout make_batch_layout(const bool present[4], int batch, int n_cu)
         if (!present[i]) continue;
         const int p = kPrimes[i];
         L.queue[i] = off;
+        off += align256((size_t)batch * sizeof(int32_t));
+        L.queue2[i] = off;
         off += align256((size_t)batch * sizeof(int32_t));
         L.gq[i] = off;
         off += align256((size_t)batch * (size_t)len_g_of(p));

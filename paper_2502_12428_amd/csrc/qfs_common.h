@@ -81,6 +81,53 @@ struct Prime {
                                          (2 * (P - 1) + 1) * (int64_t)(2 * (P - 1)) / 2 + (P - 1));
 };
 
+// Monomials of degree 4j (j = 1..P-1) whose four exponents are all <= P-1,
+// packed 8 bits per exponent, grouped by degree.  The coefficient of
+// (x1 x2 x3 x4)^(P-1) in f^(P-1) (Fedder's test) depends only on these
+// coefficients of the powers f^j: a term f[t] f^j[m - t] with m <= P-1 in
+// every exponent has m - t <= P-1 as well.
+template <int P>
+struct CapTable {
+    static constexpr int count(int n)
+    {
+        int c = 0;
+        for (int x1 = 0; x1 < P; ++x1)
+            for (int x2 = 0; x2 < P; ++x2)
+                for (int x3 = 0; x3 < P; ++x3) {
+                    const int x4 = n - x1 - x2 - x3;
+                    if (x4 >= 0 && x4 < P) ++c;
+                }
+        return c;
+    }
+    static constexpr int total()
+    {
+        int t = 0;
+        for (int j = 1; j < P; ++j) t += count(4 * j);
+        return t;
+    }
+    static constexpr int N = total();
+    uint32_t m[N];
+    int off[P], len[P];  // degree 4j: entries off[j] .. off[j] + len[j] - 1
+};
+template <int P>
+constexpr CapTable<P> make_cap_table()
+{
+    CapTable<P> t{};
+    int n = 0;
+    for (int j = 1; j < P; ++j) {
+        t.off[j] = n;
+        for (int x1 = 0; x1 < P; ++x1)
+            for (int x2 = 0; x2 < P; ++x2)
+                for (int x3 = 0; x3 < P; ++x3) {
+                    const int x4 = 4 * j - x1 - x2 - x3;
+                    if (x4 >= 0 && x4 < P)
+                        t.m[n++] = (uint32_t)x1 | ((uint32_t)x2 << 8) | ((uint32_t)x3 << 16) | ((uint32_t)x4 << 24);
+                }
+        t.len[j] = n - t.off[j];
+    }
+    return t;
+}
+
 // ---------------------------------------------------------------------------
 // Block-Toeplitz geometry for the matrix-core product C = A * g (g of degree d).
 //
@@ -128,19 +175,7 @@ struct Geo {
     static constexpr int64_t W_BYTES = (int64_t)NVP * 256;
 };
 
-// Offsets delta packed as 10-bit fields, sorted lexicographically, padded with
-// the zero offset (its W block is all zero).  Per quad: bounding box
-// (min and max per coordinate, packed) and the largest weight
-// w(delta) = 2 d1 + 2 d2 + 4 d3 over the quad.
-template <int P>
-struct DeltaTable {
-    uint32_t packed[Geo<P>::NVP];
-    int32_t toff[Geo<P>::NVP];        // tile-index offset in the padded box
-    uint32_t qmin[Geo<P>::NQ];
-    uint32_t qmax[Geo<P>::NQ];
-    int32_t qwmax[Geo<P>::NQ];
-};
-
+// Tile coordinates (or offsets) packed as three 10-bit fields.
 __host__ __device__ constexpr uint32_t pack3(int a, int b, int c)
 {
     return (uint32_t)a | ((uint32_t)b << 10) | ((uint32_t)c << 20);
@@ -148,43 +183,6 @@ __host__ __device__ constexpr uint32_t pack3(int a, int b, int c)
 __host__ __device__ constexpr int unp0(uint32_t v) { return (int)(v & 1023u); }
 __host__ __device__ constexpr int unp1(uint32_t v) { return (int)((v >> 10) & 1023u); }
 __host__ __device__ constexpr int unp2(uint32_t v) { return (int)((v >> 20) & 1023u); }
-
-template <int P>
-constexpr DeltaTable<P> make_delta_table()
-{
-    using G = Geo<P>;
-    DeltaTable<P> t{};
-    int n = 0;
-    for (int a = 0; a <= G::H1; ++a)
-        for (int b = 0; b <= G::H2; ++b)
-            for (int c = 0; c <= G::H3; ++c)
-                if (G::valid(a, b, c)) {
-                    t.packed[n] = pack3(a, b, c);
-                    t.toff[n] = (a * G::B2 + b) * G::B3 + c;
-                    ++n;
-                }
-    for (; n < G::NVP; ++n) {
-        t.packed[n] = 0;
-        t.toff[n] = 0;
-    }
-    for (int q = 0; q < G::NQ; ++q) {
-        int lo[3] = {1 << 20, 1 << 20, 1 << 20}, hi[3] = {-1, -1, -1}, wmax = 0;
-        for (int i = 0; i < 4; ++i) {
-            uint32_t v = t.packed[4 * q + i];
-            int x[3] = {unp0(v), unp1(v), unp2(v)};
-            for (int j = 0; j < 3; ++j) {
-                if (x[j] < lo[j]) lo[j] = x[j];
-                if (x[j] > hi[j]) hi[j] = x[j];
-            }
-            int w = T1 * x[0] + T2 * x[1] + T3 * x[2];
-            if (w > wmax) wmax = w;
-        }
-        t.qmin[q] = pack3(lo[0], lo[1], lo[2]);
-        t.qmax[q] = pack3(hi[0], hi[1], hi[2]);
-        t.qwmax[q] = wmax;
-    }
-    return t;
-}
 
 // ---------------------------------------------------------------------------
 // Super-tile form of the product used by the deep kernel.  Output tiles are
@@ -233,9 +231,10 @@ struct DeltaTableX {
     uint32_t packed[GeoX<P>::NVXP];       // VX with +1 on c1, c2 (pack3(d1+1, d2+1, d3))
     int32_t toff[GeoX<P>::NVXP];          // tile-index offset of delta in the box
     uint32_t widx[GeoX<P>::NVXP][2];      // W block of delta + Delta_s, 16 bits per shift (NV = zero block)
-    uint32_t qmin[GeoX<P>::NQX];          // per quad: min (offset packed), max, largest weight
+    uint32_t qmin[GeoX<P>::NQX];          // per quad: min (offset packed), max, largest and smallest weight
     uint32_t qmax[GeoX<P>::NQX];
     int32_t qwmax[GeoX<P>::NQX];
+    int32_t qwmin[GeoX<P>::NQX];
     uint32_t wnz[GeoX<P>::NQX];           // bit s: some block of the quad for shift s is nonzero
 };
 
@@ -279,7 +278,8 @@ constexpr DeltaTableX<P> make_delta_table_x()
         t.widx[n][1] = t.widx[n][0];
     }
     for (int q = 0; q < X::NQX; ++q) {
-        int lo[3] = {1 << 20, 1 << 20, 1 << 20}, hi[3] = {-(1 << 20), -(1 << 20), -(1 << 20)}, wmax = -(1 << 20);
+        int lo[3] = {1 << 20, 1 << 20, 1 << 20}, hi[3] = {-(1 << 20), -(1 << 20), -(1 << 20)}, wmax = -(1 << 20),
+            wmin = 1 << 20;
         uint32_t nz = 0;
         for (int i = 0; i < 4; ++i) {
             const uint32_t v = t.packed[4 * q + i];
@@ -290,6 +290,7 @@ constexpr DeltaTableX<P> make_delta_table_x()
             }
             const int w = T1 * x[0] + T2 * x[1] + T3 * x[2];
             if (w > wmax) wmax = w;
+            if (w < wmin) wmin = w;
             for (int s = 0; s < 4; ++s) {
                 const uint32_t wi = (t.widx[4 * q + i][s >> 1] >> (16 * (s & 1))) & 0xFFFFu;
                 if (wi != (uint32_t)X::NV) nz |= 1u << s;
@@ -298,6 +299,7 @@ constexpr DeltaTableX<P> make_delta_table_x()
         t.qmin[q] = pack3(lo[0] + 1, lo[1] + 1, lo[2]);
         t.qmax[q] = pack3(hi[0] + 1, hi[1] + 1, hi[2]);
         t.qwmax[q] = wmax;
+        t.qwmin[q] = wmin;
         t.wnz[q] = nz;
     }
     return t;

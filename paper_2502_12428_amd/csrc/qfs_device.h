@@ -24,8 +24,6 @@ __device__ inline uint8_t gload1(const uint8_t *p) { return *(const QFS_GLOBAL u
 
 __constant__ B4Table kB4 = make_b4();
 template <int P>
-__constant__ DeltaTable<P> kDT = make_delta_table<P>();
-template <int P>
 __constant__ ThetaTable<P> kTT = make_theta_table<P>();
 
 __device__ inline int wave_max(int v)
@@ -71,16 +69,40 @@ __device__ inline int pow_p_mod_p2(int b)
     return r;
 }
 
+// Compact list of the nonzero terms of f (35 coefficients in LDS) into
+// taps[0..n-1]: exponents e1, e2, e3 in bytes 0..2 and the coefficient in
+// byte 3 (e4 = 4 - e1 - e2 - e3).  Called by the first wave of the block;
+// returns n to that wave.
+__device__ inline int compact_taps(const uint8_t *f35, uint32_t *taps)
+{
+    const int lane = threadIdx.x & 63;
+    uint32_t te = 0;
+    bool nz = false;
+    if (lane < 35) {
+        const uint32_t v = f35[lane];
+        nz = v != 0;
+        te = (kB4.e[lane] & 0xFFFFFFu) | (v << 24);
+    }
+    const uint64_t bal = __ballot(nz);
+    if (nz) taps[__popcll(bal & ((1ull << lane) - 1ull))] = te;
+    return __popcll(bal);
+}
+
 // g = f^(P-1) mod P in CNS order, computed in LDS by repeated multiplication
-// with f (35 coefficients, CNS order in LDS).  b0 and b1 must each hold
-// C(4P-1,3) bytes.  Returns the buffer holding the result.  Must be called by
+// with the nonzero terms of f.  b0 and b1 must each hold C(4P-1,3) bytes,
+// taps 35 words.  Returns the buffer holding the result.  Must be called by
 // every thread of the block.
 template <int P>
-__device__ uint8_t *fpow_lds(const uint8_t *f35, uint8_t *b0, uint8_t *b1)
+__device__ uint8_t *fpow_lds(const uint8_t *f35, uint8_t *b0, uint8_t *b1, uint32_t *taps, int *ntap)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int i = tid; i < 35; i += nt) b0[i] = f35[i];
+    if (tid < 64) {
+        const int n = compact_taps(f35, taps);
+        if (tid == 0) *ntap = n;
+    }
     __syncthreads();
+    const int ntaps = *ntap;
     uint8_t *cur = b0, *nxt = b1;
     for (int j = 1; j < P - 1; ++j) {
         const int n = 4 * (j + 1);
@@ -89,11 +111,11 @@ __device__ uint8_t *fpow_lds(const uint8_t *f35, uint8_t *b0, uint8_t *b1)
             int e1, e2, e3, e4;
             cns_unrank(n, r, e1, e2, e3, e4);
             int acc = 0;
-            for (int t = 0; t < 35; ++t) {
-                const uint32_t te = kB4.e[t];
-                const int t1 = te & 255, t2 = (te >> 8) & 255, t3 = (te >> 16) & 255, t4 = te >> 24;
+            for (int k = 0; k < ntaps; ++k) {
+                const uint32_t te = taps[k];
+                const int t1 = te & 255, t2 = (te >> 8) & 255, t3 = (te >> 16) & 255, t4 = 4 - t1 - t2 - t3;
                 if (e1 >= t1 && e2 >= t2 && e3 >= t3 && e4 >= t4)
-                    acc += f35[t] * cur[cns_rank(e2 - t2, e3 - t3, e4 - t4)];
+                    acc += (int)(te >> 24) * cur[cns_rank(e2 - t2, e3 - t3, e4 - t4)];
             }
             nxt[r] = (uint8_t)(acc % P);
         }

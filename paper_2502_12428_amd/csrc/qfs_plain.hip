@@ -44,7 +44,8 @@ __global__ __launch_bounds__(256) void k_plain_start(const uint8_t *f, uint8_t *
     constexpr int d = L::d, LG = L::LG, S = d + 1;
     __shared__ __align__(16) uint8_t f35[64];
     __shared__ __align__(16) uint8_t b0[(LG + 15) / 16 * 16], b1[(LG + 15) / 16 * 16];
-    __shared__ int bad, ntaps;
+    __shared__ int bad, ntaps, fnt;
+    __shared__ uint32_t ftaps[35];
     PlainHdr *hdr = (PlainHdr *)(ws + L::hdr);
     const int tid = threadIdx.x;
     if (tid == 0) {
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(256) void k_plain_start(const uint8_t *f, uint8_t *
         if (v >= P) atomicOr(&bad, 1);
     }
     __syncthreads();
-    const uint8_t *g = fpow_lds<P>(f35, b0, b1);
+    const uint8_t *g = fpow_lds<P>(f35, b0, b1, ftaps, &fnt);
     uint8_t *gw = ws + L::g;
     uint32_t *taps = (uint32_t *)(ws + L::taps);
     uint8_t *tapv = ws + L::tapv;

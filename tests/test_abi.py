@@ -85,3 +85,27 @@ def test_host_side_argument_errors():
     assert L.qfs_height_plain(7, 1, dummy, 0, dummy, dummy, 1 << 20, nul) == qfs.QFS_EINVAL
     misaligned = ctypes.c_void_p(4096 + 8)
     assert L.qfs_height_plain(7, 1, dummy, 10, dummy, misaligned, 1 << 20, nul) == qfs.QFS_EINVAL
+
+
+def test_mfma_counts_of_both_passes():
+    for p in (3, 5, 7, 11):
+        full, band = qfs.mfma_per_surface(p), qfs.mfma_per_surface(p, band=True)
+        assert full > 0 and band > 0 and band < full
+    assert qfs.lib().qfs_mfma_per_surface(7, 2) == -1
+    assert qfs.lib().qfs_mfma_per_surface(13, 0) == -1
+
+
+def test_options():
+    assert qfs.get_option("height_band") == 1
+    qfs.set_option("height_band", 0)
+    try:
+        assert qfs.get_option("height_band") == 0
+    finally:
+        qfs.set_option("height_band", 1)
+    assert qfs.get_option("height_band") == 1
+    with pytest.raises(qfs.QfsError):
+        qfs.set_option("height_band", 2)
+    with pytest.raises(qfs.QfsError):
+        qfs.set_option("no_such_option", 1)
+    with pytest.raises(qfs.QfsError):
+        qfs.get_option("no_such_option")

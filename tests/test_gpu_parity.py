@@ -220,3 +220,30 @@ def test_height_deterministic(qfs):
     a = host(qfs.height(dev(F), 5))
     b = host(qfs.height(dev(F), 5))
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name", ["p5_batch8192", "p7_single", "p7_batch65536", "mixed4096"])
+def test_height_band_pass_matches_full_chain(qfs, name):
+    # the capped chain decides h = 2 from the window of Delta_1 the first test
+    # reads; with it switched off every deep surface runs the full chain
+    F, P, H = load_golden(name)
+    say("height with and without the capped chain: %s" % name)
+    qfs.set_option("height_band", 0)
+    try:
+        full = host(qfs.height(dev(F), dev(P), max_p=int(P.max())))
+    finally:
+        qfs.set_option("height_band", 1)
+    band = host(qfs.height(dev(F), dev(P), max_p=int(P.max())))
+    assert np.array_equal(full, H)
+    assert np.array_equal(band, H)
+
+
+@pytest.mark.parametrize("name", ["p5_batch8192", "p7_batch65536"])
+def test_height_bound_two_on_workloads(qfs, name):
+    # with b = 2 Algorithm 3 returns h for h <= 2 and infinity otherwise: the
+    # capped chain alone decides every deep surface
+    F, P, H = load_golden(name)
+    want = np.where((H == 1) | (H == 2), H, 0)
+    say("height bound 2: %s" % name)
+    got = host(qfs.height(dev(F), dev(P), bound=2, max_p=int(P.max())))
+    assert np.array_equal(got, want)

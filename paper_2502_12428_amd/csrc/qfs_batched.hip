@@ -191,13 +191,14 @@ __global__ __launch_bounds__(256) void k_plan(uint32_t *plan)
 {
     using X = GeoX<P>;
     constexpr int d = 4 * (P - 1);
-    const int kind = blockIdx.x / P, k = blockIdx.x % P;  // 0 base, 1 shell, 2 band
-    if (kind == 1 ? (k > P - 2) : (k < 1)) return;
-    const int m = kind == 1 ? (k + 2) * d + 4 : (k + 1) * d;
-    uint32_t *out = plan + (kind == 0 ? kPT<P>.boff[k] : kind == 1 ? kPT<P>.foff[k] : kPT<P>.noff[k]);
+    const int kind = blockIdx.x / P, k = blockIdx.x % P;  // 0 base, 1 shell, 2 band, 3 band shell
+    if (kind == 1 ? (k > P - 2) : kind == 3 ? (k < 1 || k > P - 2) : (k < 1)) return;
+    const int m = (k + 1) * d;
+    uint32_t *out = plan + (kind == 0 ? kPT<P>.boff[k] : kind == 1 ? kPT<P>.foff[k] : kind == 2 ? kPT<P>.noff[k]
+                                                                                          : kPT<P>.hoff[k]);
     __shared__ int cnt[256];
     const int tid = threadIdx.x;
-    if (kind != 1) {
+    if (kind == 0 || kind == 2) {
         // blocks of base units, a contiguous range of block indices per thread
         const bool band = kind == 2;
         auto keep = [&](uint32_t t) { return !band || band_tile_packed<P>(m, t); };
@@ -214,25 +215,26 @@ __global__ __launch_bounds__(256) void k_plan(uint32_t *plan)
         for (int b = b0; b < b1; ++b) off += plan_block_emit(m, b, keep, [&](int i, uint32_t t) { out[off + i] = t; });
         return;
     }
-    // shell lists: one slab c1 per thread, any order
+    // shell lists: one column slab c1 per thread, any order
+    const int cap = kind == 3 ? P * P - 1 : CAP_NONE;
+    const int cm = shell_cmax<P>(k, cap);
     const int c1 = tid;
-    const bool mine_slab = T1 * c1 <= m && c1 <= X::C1;
     int mine = 0;
-    if (mine_slab)
-        for (int c2 = 0; T1 * c1 + T2 * c2 <= m && c2 <= X::C2; ++c2) {
-            int top = (m - T1 * c1 - T2 * c2) / T3;
-            if (top > X::C3 - 1) top = X::C3 - 1;
-            mine += top + 1;
+    if (c1 <= cm)
+        for (int c2 = 0; c2 <= cm; ++c2) {
+            int lo = 0, hi = -1;
+            shell_c3_range<P>(k, cap, c1, c2, lo, hi);
+            if (hi >= lo) mine += hi - lo + 1;
         }
     cnt[c1] = mine;
     __syncthreads();
-    if (mine_slab) {
+    if (c1 <= cm) {
         int off = 0;
         for (int i = 0; i < c1; ++i) off += cnt[i];
-        for (int c2 = 0; T1 * c1 + T2 * c2 <= m && c2 <= X::C2; ++c2) {
-            int top = (m - T1 * c1 - T2 * c2) / T3;
-            if (top > X::C3 - 1) top = X::C3 - 1;
-            for (int c3 = 0; c3 <= top; ++c3) out[off++] = pack3(c1, c2, c3);
+        for (int c2 = 0; c2 <= cm; ++c2) {
+            int lo = 0, hi = -1;
+            shell_c3_range<P>(k, cap, c1, c2, lo, hi);
+            for (int c3 = lo; c3 <= hi; ++c3) out[off++] = pack3(c1, c2, c3);
         }
     }
 }
@@ -240,10 +242,10 @@ __global__ __launch_bounds__(256) void k_plan(uint32_t *plan)
 hipError_t launch_plan(int p, uint32_t *plan, hipStream_t s)
 {
     switch (p) {
-    case 3: hipLaunchKernelGGL(k_plan<3>, dim3(9), dim3(256), 0, s, plan); break;
-    case 5: hipLaunchKernelGGL(k_plan<5>, dim3(15), dim3(256), 0, s, plan); break;
-    case 7: hipLaunchKernelGGL(k_plan<7>, dim3(21), dim3(256), 0, s, plan); break;
-    case 11: hipLaunchKernelGGL(k_plan<11>, dim3(33), dim3(256), 0, s, plan); break;
+    case 3: hipLaunchKernelGGL(k_plan<3>, dim3(4 * 3), dim3(256), 0, s, plan); break;
+    case 5: hipLaunchKernelGGL(k_plan<5>, dim3(4 * 5), dim3(256), 0, s, plan); break;
+    case 7: hipLaunchKernelGGL(k_plan<7>, dim3(4 * 7), dim3(256), 0, s, plan); break;
+    case 11: hipLaunchKernelGGL(k_plan<11>, dim3(4 * 11), dim3(256), 0, s, plan); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -337,16 +339,13 @@ __device__ void init_a1(const uint8_t *g, const uint32_t *list, int ntiles, uint
     }
 }
 
-// Zero the tiles of a shell list with w(c) > n: the next product reads them as
-// zeros.  The capped chain reads only tiles whose coordinates are all <= cap.
+// Zero the tiles of a shell list: the next product reads them as zeros.
 template <int P>
-__device__ void zero_shell(const uint32_t *list, int ntiles, int n, int cap, uint8_t *A)
+__device__ void zero_shell(const uint32_t *list, int ntiles, uint8_t *A)
 {
     for (int i = threadIdx.x; i < ntiles; i += blockDim.x) {
         const uint32_t t = list[i];
-        const int c1 = unp0(t), c2 = unp1(t), c3 = unp2(t);
-        if (T1 * c1 + T2 * c2 + T3 * c3 > n && T1 * c1 <= cap && T2 * c2 <= cap && T3 * c3 <= cap)
-            gstore16(A + box_tile<P>(c1, c2, c3) * 16, v4u{0, 0, 0, 0});
+        gstore16(A + box_tile<P>(unp0(t), unp1(t), unp2(t)) * 16, v4u{0, 0, 0, 0});
     }
 }
 
@@ -394,18 +393,19 @@ __device__ __attribute__((always_inline)) inline unsigned epilogue(int c1, int c
     return packed;
 }
 
-// One wave computes NB groups of 16 base tiles and their four shifts, i.e.
-// 4 * NB output groups of A_{k+1} = A_k * g~.  Per quad of offsets delta it
-// loads one input fragment per group (the 16 tiles q - delta) and one W
-// fragment per shift (blocks W_{delta + Delta_s}), then issues up to
-// 4 * NB products D[s][tile] += W[s][(delta, s')] * A[(delta, s')][tile].
-template <int P>
-__device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *list, int nbase, int gs, int nk, int cap, const uint8_t *W,
-                         const uint8_t *__restrict__ Ain, uint8_t *Aout, bool last, const int *toff_l,
-                         const uint32_t *widx_l, const uint32_t *qbox_l, uint16_t *qlist, const EpiCtx &ec)
+// One wave computes NB groups of 16 base tiles (groups gfirst .. gfirst+NB-1
+// of the list) and their four shifts, i.e. 4 * NB output groups of
+// A_{k+1} = A_k * g~.  Per quad of offsets delta it loads one input fragment
+// per group (the 16 tiles q - delta) and one W fragment per shift (blocks
+// W_{delta + Delta_s}), then issues 4 * NB products
+// D[s][tile] += W[s][(delta, s')] * A[(delta, s')][tile].
+template <int P, int NB>
+__device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *list, int nbase, int gfirst, int nk, int cap,
+                         const uint8_t *W, const uint8_t *__restrict__ Ain, uint8_t *Aout, bool last,
+                         const int *toff_l, const uint32_t *widx_l, const uint32_t *qbox_l, uint16_t *qlist,
+                         const EpiCtx &ec)
 {
     using X = GeoX<P>;
-    constexpr int NB = DEEP_NB;
     constexpr int P2 = P * P;
     const int lane = threadIdx.x & 63, kg = lane >> 4, col = lane & 15;
 
@@ -415,7 +415,7 @@ __device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *l
     uint32_t tpk[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        const int g0 = (gs * NB + b) * 16;
+        const int g0 = (gfirst + b) * 16;
         gex[b] = g0 < nbase;
         const int idx = g0 + col;
         ok[b] = idx < nbase;
@@ -606,12 +606,21 @@ __device__ __attribute__((always_inline)) inline void run_chain(bool band, const
         uint8_t *Aout = (k & 1) ? buf1 : buf0;
         const int nbase = (int)(band ? kPT<P>.nlen[k] : kPT<P>.blen[k]);
         const uint32_t *list = plan + (band ? kPT<P>.noff[k] : kPT<P>.boff[k]);
-        const int nsets = ((nbase + 15) / 16 + DEEP_NB - 1) / DEEP_NB;
         const bool last = (k == P - 1);
         ec.win = band && last;
-        for (int gs = wave; gs < nsets; gs += DEEP_NW)
-            mfma_set<P>(list, nbase, gs, k * d, cap, W, Ain, Aout, last, toff_l, widx_l, qbox_l, qlist_w, ec);
-        if (!last) zero_shell<P>(plan + kPT<P>.foff[k], (int)kPT<P>.flen[k], (k + 1) * d, cap, Aout);
+        // whole rounds of DEEP_NB-group sets, one per wave; the groups left
+        // over go out in sets of DEEP_NB/2 so that more waves share the tail
+        const int ngroups = (nbase + 15) / 16;
+        const int rounds = ngroups / (DEEP_NB * DEEP_NW);
+        for (int i = 0; i < rounds; ++i)
+            mfma_set<P, DEEP_NB>(list, nbase, (i * DEEP_NW + wave) * DEEP_NB, k * d, cap, W, Ain, Aout, last, toff_l,
+                                 widx_l, qbox_l, qlist_w, ec);
+        constexpr int NB2 = DEEP_NB / 2;
+        for (int g = rounds * DEEP_NB * DEEP_NW + wave * NB2; g < ngroups; g += DEEP_NW * NB2)
+            mfma_set<P, NB2>(list, nbase, g, k * d, cap, W, Ain, Aout, last, toff_l, widx_l, qbox_l, qlist_w, ec);
+        if (!last)
+            zero_shell<P>(plan + (band ? kPT<P>.hoff[k] : kPT<P>.foff[k]), (int)(band ? kPT<P>.hlen[k] : kPT<P>.flen[k]),
+                          Aout);
         __syncthreads();
     }
 }
@@ -807,9 +816,14 @@ static int64_t mfma_count_p(bool band)
         const int nt = (int)tiles.size();
         if (nt != (band ? kPlanTable<P>.nlen[k] : kPlanTable<P>.blen[k])) return -1;  // list lengths disagree
         const int ngroups = (nt + 15) / 16;
-        for (int gs = 0; gs * DEEP_NB < ngroups; ++gs) {
+        const int rounds = ngroups / (DEEP_NB * DEEP_NW);
+        // (first group, groups) of every set k_deep multiplies
+        std::vector<std::pair<int, int>> sets;
+        for (int g = 0; g < rounds * DEEP_NB * DEEP_NW; g += DEEP_NB) sets.push_back({g, DEEP_NB});
+        for (int g = rounds * DEEP_NB * DEEP_NW; g < ngroups; g += DEEP_NB / 2) sets.push_back({g, DEEP_NB / 2});
+        for (const auto &st : sets) {
             int m1 = 0, m2 = 0, m3 = 0, wmin = 1 << 30, l1 = 1 << 30, l2 = 1 << 30, l3 = 1 << 30, wmax = 0;
-            for (int g = gs * DEEP_NB * 16; g < std::min(nt, (gs + 1) * DEEP_NB * 16); ++g) {
+            for (int g = st.first * 16; g < std::min(nt, (st.first + st.second) * 16); ++g) {
                 const uint32_t t = tiles[g];
                 m1 = std::max(m1, unp0(t));
                 m2 = std::max(m2, unp1(t));
@@ -825,7 +839,7 @@ static int64_t mfma_count_p(bool band)
                 nq += quad_needed(m1, m2, m3, wmin, l1, l2, l3, wmax, nk, cap, DX.qmin[q], DX.qwmax[q], DX.qmax[q],
                                   DX.qwmin[q]);
             nq += (DEEP_PF - nq % DEEP_PF) % DEEP_PF;  // null-quad padding
-            total += (int64_t)nq * 4 * DEEP_NB;
+            total += (int64_t)nq * 4 * st.second;
         }
     }
     return total;

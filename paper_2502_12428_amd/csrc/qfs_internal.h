@@ -115,14 +115,43 @@ __host__ __device__ inline bool quad_needed(int m1, int m2, int m3, int wmin, in
 // Output-tile lists of the deep kernel (packed with pack3):
 //  base list k (k = 1..P-1): base tiles of the 2x2 super-tiles of output
 //    degree n = (k+1) d: c1, c2 even, w(c) = 2 c1 + 2 c2 + 4 c3 <= n;
-//  shell list k (k = 0..P-2): all tiles c >= 0 of the box with
-//    w(c) <= (k+2) d + 4, the region the next product reads;
-//  band list k (k = 1..P-1): the base tiles of list k that band_tile keeps.
+//  shell list 0: all tiles c >= 0 of the box with w(c) <= 2d + 4 (A_1 = g~
+//    and the zeros the first product reads beyond its degree);
+//  shell list k (k = 1..P-2): the tiles with (k+1) d < w(c) <= (k+2) d + 4,
+//    zeroed after step k because step k+1 reads them;
+//  band list k (k = 1..P-1): the base tiles of list k that band_tile keeps;
+//  band shell list k (k = 1..P-2): the tiles of shell list k whose coordinates
+//    are all T_i c_i <= p^2 - 1, the only ones the capped chain reads.
 template <int P>
 struct PlanTable {
-    int64_t blen[P], boff[P], flen[P], foff[P], nlen[P], noff[P];
+    int64_t blen[P], boff[P], flen[P], foff[P], nlen[P], noff[P], hlen[P], hoff[P];
     int64_t words;
 };
+// The c3 range [lo, hi] (empty if lo > hi) of shell list k (cap = CAP_NONE)
+// or band shell list k (cap = p^2 - 1) in the column (c1, c2).
+template <int P>
+__host__ __device__ constexpr void shell_c3_range(int k, int cap, int c1, int c2, int &lo, int &hi)
+{
+    using X = GeoX<P>;
+    constexpr int d = 4 * (P - 1);
+    const int n = k == 0 ? -1 : (k + 1) * d, m = (k + 2) * d + 4;
+    const int r = T1 * c1 + T2 * c2;
+    lo = r > n ? 0 : (n - r) / T3 + 1;
+    hi = m < r ? -1 : (m - r) / T3;
+    if (hi > X::C3 - 1) hi = X::C3 - 1;
+    if (hi > cap / T3) hi = cap / T3;
+}
+// Largest c1 (and c2) of shell list k's columns.
+template <int P>
+__host__ __device__ constexpr int shell_cmax(int k, int cap)
+{
+    using X = GeoX<P>;
+    const int m = (k + 2) * (4 * (P - 1)) + 4;
+    int c = m / T1;
+    if (c > X::C1) c = X::C1;
+    if (c > cap / T1) c = cap / T1;
+    return c;
+}
 template <int P>
 constexpr int64_t base_tiles(int n)
 {
@@ -132,15 +161,15 @@ constexpr int64_t base_tiles(int n)
     return cnt;
 }
 template <int P>
-constexpr int64_t shell_tiles(int m)
+constexpr int64_t shell_tiles(int k, int cap)
 {
-    using X = GeoX<P>;
     int64_t cnt = 0;
-    for (int a = 0; a <= X::C1 && T1 * a <= m; ++a)
-        for (int b = 0; b <= X::C2 && T1 * a + T2 * b <= m; ++b) {
-            int top = (m - T1 * a - T2 * b) / T3;
-            if (top > X::C3 - 1) top = X::C3 - 1;
-            cnt += top + 1;
+    const int cm = shell_cmax<P>(k, cap);
+    for (int a = 0; a <= cm; ++a)
+        for (int b = 0; b <= cm; ++b) {
+            int lo = 0, hi = -1;
+            shell_c3_range<P>(k, cap, a, b, lo, hi);
+            if (hi >= lo) cnt += hi - lo + 1;
         }
     return cnt;
 }
@@ -184,13 +213,18 @@ constexpr PlanTable<P> make_plan_table()
     }
     for (int k = 0; k < P; ++k) {
         t.foff[k] = o;
-        t.flen[k] = k <= P - 2 ? shell_tiles<P>((k + 2) * d + 4) : 0;
+        t.flen[k] = k <= P - 2 ? shell_tiles<P>(k, CAP_NONE) : 0;
         o += t.flen[k];
     }
     for (int k = 0; k < P; ++k) {
         t.noff[k] = o;
         t.nlen[k] = k >= 1 ? band_tiles<P>((k + 1) * d) : 0;
         o += t.nlen[k];
+    }
+    for (int k = 0; k < P; ++k) {
+        t.hoff[k] = o;
+        t.hlen[k] = k >= 1 && k <= P - 2 ? shell_tiles<P>(k, P * P - 1) : 0;
+        o += t.hlen[k];
     }
     t.words = o;
     return t;

@@ -283,7 +283,8 @@ struct DeepLds {
     static constexpr int off_qlist = off_qbox + 16 * X::NQX;
     static constexpr int QSTRIDE = X::NQX + DEEP_PF;  // a wave's needed-quad list, padded
     static constexpr int off_red = off_qlist + ((2 * QSTRIDE * (DEEP_NT / 64) + 15) / 16 * 16);
-    static constexpr int bytes = off_red + 4 * 64;
+    static constexpr int off_sums = off_red + 4 * 64;
+    static constexpr int bytes = off_sums + 4 * LGA;
 };
 
 template <int P>
@@ -566,26 +567,15 @@ __device__ int theta_test_box(const uint8_t *dbox, const uint8_t *a, int *red)
     return block_sum((int)(part % P), red) % P;
 }
 
-// Copy Delta from its tile box into the Cartier-split layout used by theta_full.
+// Delta at a position x (degree D) from its tile box.
 template <int P>
-__device__ void box_to_theta(const uint8_t *dbox, const uint32_t *list, int nbase, uint8_t *dl)
-{
-    constexpr int D = 4 * P * (P - 1);
-    for (int i = threadIdx.x; i < nbase * 4; i += blockDim.x) {
-        const uint32_t t = list[i >> 2];
-        const int s = i & 3;
-        const int c1 = unp0(t) + (s & 1), c2 = unp1(t) + (s >> 1), c3 = unp2(t);
-        const v4u tile = gload16u(dbox + box_tile<P>(c1, c2, c3) * 16);
-#pragma unroll
-        for (int pos = 0; pos < 16; ++pos) {
-            const int x1 = T1 * c1 + (pos >> 3), x2 = T2 * c2 + ((pos >> 2) & 1), x3 = T3 * c3 + (pos & 3);
-            const int x4 = D - x1 - x2 - x3;
-            if (x4 < 0) continue;
-            const unsigned word = pos < 4 ? tile.x : pos < 8 ? tile.y : pos < 12 ? tile.z : tile.w;
-            gstore1(dl + theta_addr<P>(x1, x2, x3, x4), (uint8_t)((word >> (8 * (pos & 3))) & 255u));
-        }
+struct BoxDelta {
+    const uint8_t *dbox;
+    __device__ uint8_t operator()(int x1, int x2, int x3, int) const
+    {
+        return gload1(dbox + box_tile<P>(x1 >> 1, x2 >> 1, x3 >> 2) * 16 + (x1 & 1) * 8 + (x2 & 1) * 4 + (x3 & 3));
     }
-}
+};
 
 // The chain A_{k+1} = A_k * g~, k = 1..P-1, into the two tile boxes, from the
 // W blocks and g already in place: in full, or (band) only the super-tiles
@@ -646,6 +636,7 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
     uint32_t *qbox_l = (uint32_t *)(lds + L::off_qbox);
     uint16_t *qlist_l = (uint16_t *)(lds + L::off_qlist);
     int *red = (int *)(lds + L::off_red);
+    uint32_t *sums = (uint32_t *)(lds + L::off_sums);
     __shared__ int s_pos, s_err;
 
     const int tid = threadIdx.x, wave = uniform(tid >> 6);
@@ -755,12 +746,12 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
             }
             if (hh == a.bound) break;
             if (!split) {
-                box_to_theta<P>(dbox, a.plan + kPT<P>.boff[P - 1], (int)kPT<P>.blen[P - 1], dl);
+                cartier_split<P>(BoxDelta<P>{dbox}, dl);
                 split = true;
             }
             build_aperm<P>(g_l, aperm);
             __syncthreads();
-            theta_full<P>(dl, aperm, g_l);
+            theta_full<P>(dl, aperm, sums, g_l);
             __syncthreads();
         }
         if (tid == 0) a.heights[surf] = h;

@@ -372,6 +372,20 @@ struct ThetaGeo {
     static constexpr int NCP = count_cp();       // number of coarse parts c' (35 when J = 4)
     static constexpr int APERM = count_aperm();  // bytes of the permuted input vector
     static constexpr int NSIG = P * P * P * P;
+    // first column of region j in the column table, first c' of degree j
+    static constexpr int col_off(int j)
+    {
+        int o = 0;
+        for (int i = 0; i < j; ++i) o += rs(i);
+        return o;
+    }
+    static constexpr int NCOL = col_off(J);
+    static constexpr int cp_off(int j)
+    {
+        int o = 0;
+        for (int i = 0; i < j; ++i) o += (int)num_mono(i);
+        return o;
+    }
 };
 
 template <int P>
@@ -383,6 +397,7 @@ struct ThetaTable {
     int32_t cp_j[ThetaGeo<P>::NCP];
     int32_t rs[4];
     int64_t roff[4];
+    alignas(16) uint16_t sig[ThetaGeo<P>::NCOL]; // column of a region -> sigma, 4 bits per exponent; 0xFFFF = padding
 };
 
 template <int P>
@@ -407,8 +422,11 @@ constexpr ThetaTable<P> make_theta_table()
                     int e = target - a - b - c;
                     if (e < 0 || e >= P) continue;
                     int sg = (((P - 1 - a) * P + (P - 1 - b)) * P + (P - 1 - c)) * P + (P - 1 - e);
+                    t.sig[TG::col_off(j) + s_list_n] = (uint16_t)((P - 1 - a) | ((P - 1 - b) << 4) |
+                                                                  ((P - 1 - c) << 8) | ((P - 1 - e) << 12));
                     t.sidx[sg] = (int16_t)s_list_n++;
                 }
+        for (int k = s_list_n; k < TG::rs(j); ++k) t.sig[TG::col_off(j) + k] = 0xFFFF;
         // c' in B_j (descending lex) and their a_perm segments
         for (int c1 = j; c1 >= 0; --c1)
             for (int c2 = j - c1; c2 >= 0; --c2)

@@ -127,18 +127,6 @@ __device__ uint8_t *fpow_lds(const uint8_t *f35, uint8_t *b0, uint8_t *b1, uint3
     return cur;
 }
 
-// Address of the Delta coefficient at 4-d position x (sum D) in the
-// Cartier-split layout: region j = |x mod p| / p, row rank(x div p), column
-// sidx(x mod p).
-template <int P>
-__device__ inline int64_t theta_addr(int x1, int x2, int x3, int x4)
-{
-    const int s1 = x1 % P, s2 = x2 % P, s3 = x3 % P, s4 = x4 % P;
-    const int j = (s1 + s2 + s3 + s4) / P;
-    const int code = ((s1 * P + s2) * P + s3) * P + s4;
-    return kTT<P>.roff[j] + cns_rank(x2 / P, x3 / P, x4 / P) * kTT<P>.rs[j] + kTT<P>.sidx[code];
-}
-
 __device__ inline unsigned dot16(const v4u a, const v4u b, unsigned acc)
 {
     acc = __builtin_amdgcn_udot4(a.x, b.x, acc, false);
@@ -160,55 +148,117 @@ __device__ inline void build_aperm(const uint8_t *a_cns, uint8_t *aperm)
     }
 }
 
-// out[r] = theta(a)[r] mod P for r in B_d (CNS order, LDS), from a_perm (LDS)
-// and Delta in the Cartier-split layout (global):
-//   theta(a)[r] = sum_{c' <= r} < a_perm[c'] , DeltaRow_j(r - c') >.
-template <int P>
-__device__ inline void theta_full(const uint8_t *__restrict__ dl, const uint8_t *aperm, uint8_t *out)
+// Delta in the Cartier-split layout dl (global), built by 16-byte chunks:
+// chunk m of row y in region j holds Delta[p y + sigma] for the region's
+// columns 16m .. 16m+15 (sigma from the column table, zero for padding).
+// src(x1, x2, x3, x4) returns Delta at a position of degree D.
+template <int P, class Src>
+__device__ inline void cartier_split(Src &&src, uint8_t *dl)
 {
     using TG = ThetaGeo<P>;
     constexpr int d = TG::d;
-    constexpr int LG = (int)num_mono(d);
-    for (int r = threadIdx.x; r < LG; r += blockDim.x) {
-        int r1, r2, r3, r4;
-        cns_unrank(d, r, r1, r2, r3, r4);
-        unsigned acc = 0;
-        for (int cp = 0; cp < TG::NCP; ++cp) {
-            const uint32_t c = kTT<P>.cprime[cp];
-            const int c1 = c & 255, c2 = (c >> 8) & 255, c3 = (c >> 16) & 255, c4 = c >> 24;
-            if (r1 < c1 || r2 < c2 || r3 < c3 || r4 < c4) continue;
-            const int j = kTT<P>.cp_j[cp];
-            const int rsj = kTT<P>.rs[j];
-            const uint8_t *row = dl + kTT<P>.roff[j] + cns_rank(r2 - c2, r3 - c3, r4 - c4) * rsj;
-            const uint8_t *av = aperm + kTT<P>.cp_seg[cp];
-            for (int k = 0; k < rsj; k += 16)
-                acc = dot16(gload16u(row + k), *(const v4u *)(av + k), acc);
+    constexpr int64_t NCH = TG::BYTES / 16;
+    for (int64_t ch = threadIdx.x; ch < NCH; ch += blockDim.x) {
+        int j = 0;
+#pragma unroll
+        for (int i = 1; i < TG::J; ++i)
+            if (ch * 16 >= kTT<P>.roff[i]) j = i;
+        const int nc = kTT<P>.rs[j] / 16;
+        const int64_t local = ch - kTT<P>.roff[j] / 16;
+        const int y = (int)(local / nc), m = (int)(local % nc);
+        int y1, y2, y3, y4;
+        cns_unrank(d - j, y, y1, y2, y3, y4);
+        int cb = 0;
+#pragma unroll
+        for (int i = 1; i < TG::J; ++i)
+            if (j == i) cb = TG::col_off(i);
+        // the chunk's 16 columns (two 16-byte loads); column 16m is never padding
+        const v4u *sg = (const v4u *)(kTT<P>.sig + cb + 16 * m);
+        const v4u s0 = sg[0], s1 = sg[1];
+        const unsigned sw[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+        const unsigned first = sw[0] & 0xFFFFu;
+        // all 16 loads are issued unconditionally (padding reads column 16m's position) and masked after
+        unsigned b[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const unsigned raw = (sw[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
+            const unsigned s = raw == 0xFFFFu ? first : raw;
+            b[q] = src(P * y1 + (int)(s & 15), P * y2 + (int)((s >> 4) & 15), P * y3 + (int)((s >> 8) & 15),
+                       P * y4 + (int)(s >> 12));
+            if (raw == 0xFFFFu) b[q] = 0;
         }
-        out[r] = (uint8_t)(acc % P);
+        unsigned w[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < 16; ++q) w[q >> 2] |= b[q] << (8 * (q & 3));
+        gstore16(dl + ch * 16, v4u{w[0], w[1], w[2], w[3]});
     }
 }
 
-// c(theta(a)) = theta(a)[e] mod P, the only coefficient the height test reads
-// (Section 3.4): a block-wide dot product over the NCP segments.
-template <int P>
-__device__ inline int theta_test(const uint8_t *__restrict__ dl, const uint8_t *aperm, int *red)
+// theta(a) for the coarse parts of degree J0: row y of region J0 (Delta at
+// p y + sigma) meets the a_perm segment of every c' of degree J0 at output
+// r = y + c'.  Each row is read once (coalesced across the block); the dot
+// products are added into the 32-bit sums in LDS.
+template <int P, int J0>
+__device__ __attribute__((always_inline)) inline void theta_region(const uint8_t *__restrict__ dl,
+                                                                   const uint8_t *aperm, uint32_t *sums)
 {
     using TG = ThetaGeo<P>;
-    unsigned part = 0;
-    // one 16-byte chunk per thread iteration; chunk -> c' by scanning segments
-    for (int ch = threadIdx.x; ch < TG::APERM / 16; ch += blockDim.x) {
-        const int off = ch * 16;
-        int cp = 0;
-        while (cp + 1 < TG::NCP && kTT<P>.cp_seg[cp + 1] <= off) ++cp;
-        const uint32_t c = kTT<P>.cprime[cp];
-        const int c1 = c & 255, c2 = (c >> 8) & 255, c3 = (c >> 16) & 255, c4 = c >> 24;
-        const int j = kTT<P>.cp_j[cp];
-        const int64_t row = kTT<P>.roff[j] +
-                            cns_rank(P - 1 - c2, P - 1 - c3, P - 1 - c4) * kTT<P>.rs[j];
-        (void)c1;
-        part = dot16(gload16u(dl + row + (off - kTT<P>.cp_seg[cp])), *(const v4u *)(aperm + off), part);
+    constexpr int d = TG::d, RS = TG::rs(J0), NC = RS / 16, NCPJ = (int)num_mono(J0), CP0 = TG::cp_off(J0);
+    constexpr int NROW = (int)num_mono(d - J0);
+    constexpr int64_t ROFF = TG::region_off(J0);
+    constexpr int KB = NC < 8 ? NC : 8;
+    for (int y = threadIdx.x; y < NROW; y += blockDim.x) {
+        int y1, y2, y3, y4;
+        cns_unrank(d - J0, y, y1, y2, y3, y4);
+        const uint8_t *row = dl + ROFF + (int64_t)y * RS;
+        unsigned dots[NCPJ];
+#pragma unroll
+        for (int c = 0; c < NCPJ; ++c) dots[c] = 0;
+        for (int k0 = 0; k0 < NC; k0 += KB) {
+            v4u rv[KB];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) rv[k] = (k0 + k < NC) ? gload16u(row + 16 * (k0 + k)) : v4u{0, 0, 0, 0};
+#pragma unroll
+            for (int c = 0; c < NCPJ; ++c) {
+                const uint8_t *av = aperm + kTT<P>.cp_seg[CP0 + c] + 16 * k0;
+#pragma unroll
+                for (int k = 0; k < KB; ++k)
+                    if (k0 + k < NC) dots[c] = dot16(rv[k], *(const v4u *)(av + 16 * k), dots[c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NCPJ; ++c) {
+            const uint32_t cp = kTT<P>.cprime[CP0 + c];
+            atomicAdd(&sums[cns_rank(y2 + (int)((cp >> 8) & 255), y3 + (int)((cp >> 16) & 255), y4 + (int)(cp >> 24))],
+                      dots[c]);
+        }
     }
-    return block_sum((int)(part % P), red) % P;
+}
+
+template <int P, int J0>
+__device__ __attribute__((always_inline)) inline void theta_regions(const uint8_t *dl, const uint8_t *aperm,
+                                                                    uint32_t *sums)
+{
+    if constexpr (J0 < ThetaGeo<P>::J) {
+        theta_region<P, J0>(dl, aperm, sums);
+        theta_regions<P, J0 + 1>(dl, aperm, sums);
+    }
+}
+
+// out[r] = theta(a)[r] mod P for r in B_d (CNS order, LDS), from a_perm (LDS)
+// and Delta in the Cartier-split layout (global):
+//   theta(a)[r] = sum over c' <= r of < a_perm[c'] , DeltaRow_j(r - c') >
+// (Section 3.4, with the matches of Section 4.2).  sums: C(4P-1,3) words of
+// LDS.  Must be called by every thread of the block.
+template <int P>
+__device__ inline void theta_full(const uint8_t *__restrict__ dl, const uint8_t *aperm, uint32_t *sums, uint8_t *out)
+{
+    constexpr int LG = (int)num_mono(ThetaGeo<P>::d);
+    for (int i = threadIdx.x; i < LG; i += blockDim.x) sums[i] = 0;
+    __syncthreads();
+    theta_regions<P, 0>(dl, aperm, sums);
+    __syncthreads();
+    for (int i = threadIdx.x; i < LG; i += blockDim.x) out[i] = (uint8_t)(sums[i] % P);
 }
 
 }  // namespace qfs

@@ -9,6 +9,16 @@ namespace qfs {
 
 constexpr int THETA_NT = 512;
 
+// Delta at a position x (degree D) from the caller's CNS-ordered array, reduced mod P.
+template <int P>
+struct CnsDelta {
+    const uint8_t *ds;
+    __device__ uint8_t operator()(int, int x2, int x3, int x4) const
+    {
+        return (uint8_t)(gload1(ds + cns_rank(x2, x3, x4)) % P);
+    }
+};
+
 template <int P>
 __global__ __launch_bounds__(THETA_NT) void k_theta(int batch, const uint8_t *__restrict__ delta,
                                                      const uint8_t *__restrict__ a, uint8_t *__restrict__ out,
@@ -18,24 +28,21 @@ __global__ __launch_bounds__(THETA_NT) void k_theta(int batch, const uint8_t *__
     using TG = ThetaGeo<P>;
     constexpr int LG = PR::len_g;
     constexpr int LGA = (LG + 15) / 16 * 16;
-    constexpr int D = PR::D;
     extern __shared__ __align__(16) uint8_t lds[];
+    constexpr int APA = (TG::APERM + 15) / 16 * 16;
     uint8_t *a_l = lds;
     uint8_t *aperm = lds + LGA;
+    uint32_t *sums = (uint32_t *)(lds + LGA + APA);
     uint8_t *dl = scratch + (size_t)blockIdx.x * stride;
     for (int surf = blockIdx.x; surf < batch; surf += gridDim.x) {
         const uint8_t *ds = delta + (size_t)surf * PR::len_D;
-        for (int64_t i = threadIdx.x; i < PR::len_D; i += THETA_NT) {
-            int x1, x2, x3, x4;
-            cns_unrank(D, i, x1, x2, x3, x4);
-            dl[theta_addr<P>(x1, x2, x3, x4)] = (uint8_t)(ds[i] % P);
-        }
+        cartier_split<P>(CnsDelta<P>{ds}, dl);
         for (int i = threadIdx.x; i < LG; i += THETA_NT) a_l[i] = (uint8_t)(a[(size_t)surf * LG + i] % P);
         __syncthreads();
         for (int it = 0; it < iters; ++it) {
             build_aperm<P>(a_l, aperm);
             __syncthreads();
-            theta_full<P>(dl, aperm, a_l);
+            theta_full<P>(dl, aperm, sums, a_l);
             __syncthreads();
         }
         for (int i = threadIdx.x; i < LG; i += THETA_NT) out[(size_t)surf * LG + i] = a_l[i];
@@ -46,7 +53,8 @@ __global__ __launch_bounds__(THETA_NT) void k_theta(int batch, const uint8_t *__
 template <int P>
 static size_t theta_lds()
 {
-    return (size_t)((Prime<P>::len_g + 15) / 16 * 16) + (size_t)((ThetaGeo<P>::APERM + 15) / 16 * 16);
+    constexpr size_t LGA = (Prime<P>::len_g + 15) / 16 * 16;
+    return LGA + (size_t)((ThetaGeo<P>::APERM + 15) / 16 * 16) + 4 * LGA;
 }
 
 size_t theta_scratch_bytes(int p)
@@ -60,6 +68,18 @@ size_t theta_scratch_bytes(int p)
     return 0;
 }
 
+template <int P>
+static hipError_t launch_theta_p(int grid, hipStream_t s, int batch, const uint8_t *delta, const uint8_t *a,
+                                 uint8_t *out, int iters, uint8_t *scratch, size_t stride)
+{
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void *)k_theta<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)theta_lds<P>());
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(k_theta<P>, dim3(grid), dim3(THETA_NT), theta_lds<P>(), s, batch, delta, a, out, iters, scratch,
+                       stride);
+    return hipGetLastError();
+}
+
 hipError_t launch_theta(int p, int batch, const uint8_t *delta, const uint8_t *a, uint8_t *out, int iters,
                         uint8_t *scratch, int nslots, hipStream_t s)
 {
@@ -67,13 +87,12 @@ hipError_t launch_theta(int p, int batch, const uint8_t *delta, const uint8_t *a
     const int grid = batch < nslots ? batch : nslots;
     const size_t stride = theta_scratch_bytes(p);
     switch (p) {
-    case 3: hipLaunchKernelGGL(k_theta<3>, dim3(grid), dim3(THETA_NT), theta_lds<3>(), s, batch, delta, a, out, iters, scratch, stride); break;
-    case 5: hipLaunchKernelGGL(k_theta<5>, dim3(grid), dim3(THETA_NT), theta_lds<5>(), s, batch, delta, a, out, iters, scratch, stride); break;
-    case 7: hipLaunchKernelGGL(k_theta<7>, dim3(grid), dim3(THETA_NT), theta_lds<7>(), s, batch, delta, a, out, iters, scratch, stride); break;
-    case 11: hipLaunchKernelGGL(k_theta<11>, dim3(grid), dim3(THETA_NT), theta_lds<11>(), s, batch, delta, a, out, iters, scratch, stride); break;
-    default: return hipErrorInvalidValue;
+    case 3: return launch_theta_p<3>(grid, s, batch, delta, a, out, iters, scratch, stride);
+    case 5: return launch_theta_p<5>(grid, s, batch, delta, a, out, iters, scratch, stride);
+    case 7: return launch_theta_p<7>(grid, s, batch, delta, a, out, iters, scratch, stride);
+    case 11: return launch_theta_p<11>(grid, s, batch, delta, a, out, iters, scratch, stride);
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 }  // namespace qfs

@@ -260,7 +260,7 @@ hipError_t launch_plan(int p, uint32_t *plan, hipStream_t s)
 #define QFS_DEEP_NT 512
 #endif
 #ifndef QFS_DEEP_PF
-#define QFS_DEEP_PF 3
+#define QFS_DEEP_PF 4
 #endif
 constexpr int DEEP_NT = QFS_DEEP_NT, DEEP_NW = DEEP_NT / 64, DEEP_NB = 4, DEEP_PF = QFS_DEEP_PF;
 
@@ -484,48 +484,63 @@ __device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *l
 #pragma unroll
     for (int b = 0; b < NB; ++b) boff[b] = (uint32_t)base[b] * 16u;
     const uint32_t wrow = (uint32_t)col * 16u;
-    // input fragments of the list entry i (clamped to the last entry)
-#define QFS_LOAD_B(BF, I)                                                                          \
+    // Software pipeline over the list.  Slot j holds the input fragments of one
+    // entry (loaded DEEP_PF entries ahead) with that entry's packed W-block
+    // indices; the W fragments of the next entry are read from LDS while the
+    // current entry's products issue, so no LDS round trip sits right before
+    // the matrix instructions.
+    // slot J <- list entry I (clamped to the last entry): W indices and input fragments
+#define QFS_LOAD_B(J, I)                                                                           \
     do {                                                                                           \
         const int q_ = uniform(qlist[(I) < nq ? (I) : nq - 1]);                                    \
         const uint32_t to_ = (uint32_t)toff_l[4 * q_ + kg] * 16u;                                  \
-        _Pragma("unroll") for (int b = 0; b < NB; ++b) BF[b] = gload16(Ain + (boff[b] - to_));     \
+        wa[J] = widx_l[2 * (4 * q_ + kg)];                                                         \
+        wb[J] = widx_l[2 * (4 * q_ + kg) + 1];                                                     \
+        _Pragma("unroll") for (int b = 0; b < NB; ++b) bf[J][b] = gload16(Ain + (boff[b] - to_));  \
     } while (0)
-    // W fragments of list entry i for the four shifts, then the 4 x NB products
-#define QFS_PRODUCTS(BF, I)                                                                                \
+    // W fragments (four shifts) of the entry in slot J into buffer K
+#define QFS_LOAD_W(K, J)                                                                                   \
     do {                                                                                                   \
-        const int q_ = uniform(qlist[I]);                                                                  \
-        const uint32_t w01_ = widx_l[2 * (4 * q_ + kg)], w23_ = widx_l[2 * (4 * q_ + kg) + 1];              \
-        v4i wf_[4];                                                                                        \
         _Pragma("unroll") for (int s = 0; s < 4; ++s)                                                      \
         {                                                                                                  \
-            const uint32_t wi = ((s < 2 ? w01_ : w23_) >> (16 * (s & 1))) & 0xFFFFu;                        \
-            wf_[s] = w_in_lds<P>() ? *(const v4i *)(W + wi * 256u + wrow) : gload16(W + wi * 256u + wrow);  \
+            const uint32_t wi = ((s < 2 ? wa[J] : wb[J]) >> (16 * (s & 1))) & 0xFFFFu;                      \
+            wf[K][s] = w_in_lds<P>() ? *(const v4i *)(W + wi * 256u + wrow) : gload16(W + wi * 256u + wrow); \
         }                                                                                                  \
-        _Pragma("unroll") for (int s = 0; s < 4; ++s)                                                      \
-            _Pragma("unroll") for (int b = 0; b < NB; ++b)                                                 \
-                acc[s][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(wf_[s], BF[b], acc[s][b], 0, 0, 0);       \
+    } while (0)
+    // the 4 x NB products of the entry in slot J with W buffer K
+#define QFS_PRODUCTS(K, J)                                                                         \
+    do {                                                                                           \
+        _Pragma("unroll") for (int s = 0; s < 4; ++s)                                              \
+            _Pragma("unroll") for (int b = 0; b < NB; ++b)                                         \
+                acc[s][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(wf[K][s], bf[J][b], acc[s][b], 0, 0, 0); \
     } while (0)
 
-    // DEEP_PF fragment sets rotate; each is refilled DEEP_PF entries ahead of its use
+    static_assert(DEEP_PF % 2 == 0, "W buffers alternate per entry");
     if (nq > 0) {
-        v4i bf[DEEP_PF][NB];
+        v4i bf[DEEP_PF][NB], wf[2][4];
+        uint32_t wa[DEEP_PF], wb[DEEP_PF];
 #pragma unroll
         for (int j = 0; j < DEEP_PF; ++j) {
-            QFS_LOAD_B(bf[j], j);
+            QFS_LOAD_B(j, j);
             __builtin_amdgcn_sched_barrier(0);
         }
+        QFS_LOAD_W(0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        // at the top of an iteration slot j holds entry i + j
         for (int i = 0; i < nq; i += DEEP_PF) {
 #pragma unroll
             for (int j = 0; j < DEEP_PF; ++j) {
-                QFS_PRODUCTS(bf[j], i + j);
+                QFS_LOAD_W((j + 1) & 1, (j + 1) % DEEP_PF);
                 __builtin_amdgcn_sched_barrier(0);
-                QFS_LOAD_B(bf[j], i + j + DEEP_PF);
+                QFS_PRODUCTS(j & 1, j);
+                __builtin_amdgcn_sched_barrier(0);
+                QFS_LOAD_B(j, i + j + DEEP_PF);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
 #undef QFS_LOAD_B
+#undef QFS_LOAD_W
 #undef QFS_PRODUCTS
 
     constexpr int64_t SH1 = (int64_t)X::B2 * X::B3, SH2 = X::B3;

@@ -189,6 +189,23 @@ def main():
     step_ms = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
     heights = h.cpu().numpy()
 
+    # the same steps as hipGraph replays (the library captures the launch
+    # sequence the second time it meets the same arguments)
+    graph = None
+    if qfs.get_option("height_graph") == 1:
+        out_h = torch.empty(B, dtype=torch.int32, device="cuda")
+        for _ in range(2):
+            qfs.height(f, pt, max_p=p, workspace=ws, out=out_h)
+        torch.cuda.synchronize()
+        tg0 = time.perf_counter()
+        for _ in range(args.steps):
+            qfs.height(f, pt, max_p=p, workspace=ws, out=out_h)
+        torch.cuda.synchronize()
+        tg1 = time.perf_counter()
+        graph = {"ms_per_step": 1e3 * (tg1 - tg0) / args.steps, "value": B * args.steps / (tg1 - tg0),
+                 "graphs_cached": qfs.get_option("height_graphs_cached"),
+                 "agrees": bool(np.array_equal(out_h.cpu().numpy(), heights))}
+
     parity = "unchecked"
     gold = os.path.join(ROOT, "tests", "golden", "heights_%s.npz" % args.workload)
     if os.path.exists(gold):
@@ -277,6 +294,7 @@ def main():
         },
         "stage_ms_per_step": per_call,
         "per_prime": per_prime,
+        "graph_replay": graph,
     }
 
     if not args.no_baselines:

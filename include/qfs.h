@@ -123,6 +123,14 @@ int qfs_theta(int p, int batch, const uint8_t *delta, const uint8_t *a, uint8_t 
  *            prime outside {3,5,7,11} or above max_p, QFS_EINVAL for a
  *            coefficient >= p, QFS_EARITH for a failed exactness check).
  * The workspace must hold qfs_height_workspace_bytes(batch, max_p) bytes.
+ * Launches: Fedder's test, g for the deep surfaces, then per prime the
+ * capped-chain kernel and the full-chain kernel.  With option "height_graph"
+ * (default on) the whole sequence is captured into a hipGraph the second
+ * time an argument set (every pointer and size) is met, up to 8 cached with
+ * the least recently used evicted, and later calls with the same arguments
+ * replay it on `stream`; the library
+ * holds these graphs until qfs_shutdown().  While stage timing is enabled the
+ * sequence is launched directly instead.
  * ---------------------------------------------------------------------- */
 size_t qfs_height_workspace_bytes(int batch, int max_p);
 int qfs_height(int batch, const int32_t *p, const uint8_t *f, int bound, int max_p, int32_t *heights,
@@ -164,6 +172,9 @@ int64_t qfs_mfma_per_surface(int p, int pass);
  *     theta test reads (Section 3.4: c(theta(g)) = sum_c g[c] Delta[(p+1)e-c]),
  *     and runs the full chain only for surfaces of height > 2.  0 runs the
  *     full chain for every surface.  Heights are the same either way.
+ *   "height_graph" (default 1): replay cached hipGraphs of the qfs_height
+ *     launch sequence (see qfs_height); 0 launches the kernels directly.
+ *   "height_graphs_cached" (read only): number of graphs in the cache.
  * qfs_set_option returns QFS_OK or QFS_EINVAL (unknown name or value);
  * qfs_get_option returns the value, or QFS_EINVAL for an unknown name. */
 int qfs_set_option(const char *name, int64_t value);
@@ -172,7 +183,8 @@ int64_t qfs_get_option(const char *name);
 /* Message for the last error returned in the calling thread ("" if none). */
 const char *qfs_last_error(void);
 
-/* Releases host-side caches; the library holds no device memory. */
+/* Waits for the device, then releases the graph cache and the library's
+ * capture streams.  The library holds no device memory of its own. */
 void qfs_shutdown(void);
 
 #ifdef __cplusplus

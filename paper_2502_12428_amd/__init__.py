@@ -170,8 +170,9 @@ def theta(delta, a, p, iters=1, workspace=None):
     return out
 
 
-def height(f, p, bound=10, max_p=None, workspace=None):
-    """Heights of the quartics in f (uint8 [B,35] on the GPU); p is an int or an int32 tensor [B]."""
+def height(f, p, bound=10, max_p=None, workspace=None, out=None):
+    """Heights of the quartics in f (uint8 [B,35] on the GPU); p is an int or an int32 tensor [B].
+    out: optional int32 [B] device tensor to write (repeated calls with the same tensors replay one graph)."""
     f = _device_u8(f, "f")
     B = f.shape[0]
     if isinstance(p, torch.Tensor):
@@ -182,7 +183,12 @@ def height(f, p, bound=10, max_p=None, workspace=None):
     else:
         pt = torch.full((B,), int(p), dtype=torch.int32, device=f.device)
         max_p = max_p or int(p)
-    h = torch.empty(B, dtype=torch.int32, device=f.device)
+    if out is None:
+        h = torch.empty(B, dtype=torch.int32, device=f.device)
+    else:
+        if out.dtype != torch.int32 or out.device != f.device or out.numel() != B or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32 tensor of %d elements on %s" % (B, f.device))
+        h = out
     ws = (workspace or _ws).get(lib().qfs_height_workspace_bytes(B, int(max_p)), f.device)
     _check(lib().qfs_height(B, _ptr(pt), _ptr(f), int(bound), int(max_p), _ptr(h), _ptr(ws), ws.numel(),
                             _stream()))

@@ -20,6 +20,7 @@ thread_local char g_err[512] = "";
 
 // process-wide options (qfs_set_option)
 std::atomic<bool> g_opt_height_band{true};
+std::atomic<bool> g_opt_height_graph{true};
 
 int fail(int code, const char *fmt, ...)
 {
@@ -111,6 +112,39 @@ int hip_fail(hipError_t e, const char *what)
     return fail(QFS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+// ---- graphs of the qfs_height launch sequence, keyed by every argument ----
+struct GraphKey {
+    int dev, batch, bound, max_p, band;
+    const void *p, *f, *h, *ws;
+    size_t ws_bytes;
+    bool operator==(const GraphKey &o) const
+    {
+        return dev == o.dev && batch == o.batch && bound == o.bound && max_p == o.max_p && band == o.band &&
+               p == o.p && f == o.f && h == o.h && ws == o.ws && ws_bytes == o.ws_bytes;
+    }
+};
+struct GraphEntry {
+    GraphKey key;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    uint64_t used;
+};
+constexpr size_t GRAPH_CACHE = 8;
+constexpr int MAX_DEV = 16;
+struct GraphCache {
+    std::mutex m;
+    std::vector<GraphEntry> v;
+    std::vector<GraphKey> seen;     // argument sets met once: captured when they come back
+    hipStream_t cap[MAX_DEV] = {};  // capture streams (default priority), one per device
+    uint64_t tick = 0;
+} g_graphs;
+
+void destroy_entry(GraphEntry &en)
+{
+    hipGraphExecDestroy(en.exec);
+    hipGraphDestroy(en.graph);
+}
+
 }  // namespace
 
 extern "C" {
@@ -142,7 +176,19 @@ int64_t qfs_len_delta(int p) { return supported(p) ? num_mono(4 * p * (p - 1)) :
 
 const char *qfs_last_error(void) { return g_err; }
 
-void qfs_shutdown(void) {}
+void qfs_shutdown(void)
+{
+    std::lock_guard<std::mutex> lk(g_graphs.m);
+    if (!g_graphs.v.empty()) hipDeviceSynchronize();
+    for (GraphEntry &en : g_graphs.v) destroy_entry(en);
+    g_graphs.v.clear();
+    g_graphs.seen.clear();
+    for (int d = 0; d < MAX_DEV; ++d)
+        if (g_graphs.cap[d]) {
+            hipStreamDestroy(g_graphs.cap[d]);
+            g_graphs.cap[d] = nullptr;
+        }
+}
 
 // ---------------------------------------------------------------------------
 size_t qfs_delta1_workspace_bytes(int p, int batch)
@@ -252,28 +298,12 @@ size_t qfs_height_workspace_bytes(int batch, int max_p)
     return make_batch_layout(present, batch, device_cus()).total;
 }
 
-int qfs_height(int batch, const int32_t *p, const uint8_t *f, int bound, int max_p, int32_t *heights, void *ws,
-               size_t ws_bytes, hipStream_t stream)
+// The launch sequence of qfs_height on `stream` (validated arguments).
+static int enqueue_height(int batch, const int32_t *p, const uint8_t *f, int bound, const BatchLayout &L,
+                          int32_t *heights, uint8_t *w, bool band, int gpow_wg, hipStream_t stream, ProfCall &prof)
 {
-    g_err[0] = 0;
-    if (batch < 0) return fail(QFS_EINVAL, "qfs_height: batch=%d < 0", batch);
-    if (bound < 1 || bound > 10) return fail(QFS_EINVAL, "qfs_height: bound=%d outside 1..10", bound);
-    if (max_p < 3 || max_p > 11 || !supported(max_p))
-        return fail(QFS_EUNSUPPORTED, "qfs_height: max_p=%d not in {3,5,7,11}", max_p);
-    if (batch == 0) return QFS_OK;
-    if (!p || !f || !heights || !ws) return fail(QFS_EINVAL, "qfs_height: null pointer argument");
-    if (!aligned(ws)) return fail(QFS_EINVAL, "qfs_height: workspace not 256-byte aligned");
-    const int ncu = device_cus();
-    if (ncu <= 0) return fail(QFS_EDEVICE, "qfs_height: no HIP device");
-    bool present[4];
-    present_upto(max_p, present);
-    const BatchLayout L = make_batch_layout(present, batch, ncu);
-    if (ws_bytes < L.total)
-        return fail(QFS_ENOMEM, "qfs_height: workspace %zu bytes < %zu needed", ws_bytes, L.total);
-    uint8_t *w = (uint8_t *)ws;
     int32_t *counters = (int32_t *)(w + L.counters);
     hipError_t e;
-    ProfCall prof(stream);
     prof.mark(-1);
     if ((e = launch_reset(counters, stream)) != hipSuccess) return hip_fail(e, "reset");
     Stage1Args s1{};
@@ -294,8 +324,7 @@ int qfs_height(int batch, const int32_t *p, const uint8_t *f, int bound, int max
     s1.present_mask = mask;
     if ((e = launch_stage1(s1, stream)) != hipSuccess) return hip_fail(e, "stage1");
     for (int i = 0; i < 4; ++i)
-        if (L.present[i] && (e = launch_gpow(kPrimes[i], s1, gpow_workgroups(batch), stream)) != hipSuccess)
-            return hip_fail(e, "g");
+        if (L.present[i] && (e = launch_gpow(kPrimes[i], s1, gpow_wg, stream)) != hipSuccess) return hip_fail(e, "g");
     prof.mark(0);
     for (int i = 0; i < 4; ++i) {
         if (!L.present[i]) continue;
@@ -316,7 +345,6 @@ int qfs_height(int batch, const int32_t *p, const uint8_t *f, int bound, int max
         const int nslots = batch < L.nslots[i] ? batch : L.nslots[i];
         // the capped chain decides h = 2 for every deep surface; the rest take
         // the full chain in a second launch (balanced over all workgroups)
-        const bool band = g_opt_height_band.load() && bound >= 2;
         if (band) {
             da.zero_halo = 1;
             if ((e = launch_deep(pp, true, da, nslots, stream)) != hipSuccess) return hip_fail(e, "deep band");
@@ -328,6 +356,87 @@ int qfs_height(int batch, const int32_t *p, const uint8_t *f, int bound, int max
         prof.mark(6 + i);
     }
     return QFS_OK;
+}
+
+int qfs_height(int batch, const int32_t *p, const uint8_t *f, int bound, int max_p, int32_t *heights, void *ws,
+               size_t ws_bytes, hipStream_t stream)
+{
+    g_err[0] = 0;
+    if (batch < 0) return fail(QFS_EINVAL, "qfs_height: batch=%d < 0", batch);
+    if (bound < 1 || bound > 10) return fail(QFS_EINVAL, "qfs_height: bound=%d outside 1..10", bound);
+    if (max_p < 3 || max_p > 11 || !supported(max_p))
+        return fail(QFS_EUNSUPPORTED, "qfs_height: max_p=%d not in {3,5,7,11}", max_p);
+    if (batch == 0) return QFS_OK;
+    if (!p || !f || !heights || !ws) return fail(QFS_EINVAL, "qfs_height: null pointer argument");
+    if (!aligned(ws)) return fail(QFS_EINVAL, "qfs_height: workspace not 256-byte aligned");
+    const int ncu = device_cus();
+    if (ncu <= 0) return fail(QFS_EDEVICE, "qfs_height: no HIP device");
+    bool present[4];
+    present_upto(max_p, present);
+    const BatchLayout L = make_batch_layout(present, batch, ncu);
+    if (ws_bytes < L.total)
+        return fail(QFS_ENOMEM, "qfs_height: workspace %zu bytes < %zu needed", ws_bytes, L.total);
+    const bool band = g_opt_height_band.load() && bound >= 2;
+    const int gwg = gpow_workgroups(batch);
+    for (int i = 0; i < 4; ++i) {
+        hipError_t e;
+        if (L.present[i] && (e = prepare_deep(kPrimes[i])) != hipSuccess) return hip_fail(e, "deep attributes");
+    }
+    ProfCall prof(stream);
+    if (!g_opt_height_graph.load() || prof.on)
+        return enqueue_height(batch, p, f, bound, L, heights, (uint8_t *)ws, band, gwg, stream, prof);
+
+    // replay the graph of this exact call, or capture it on a library stream first
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEV) return fail(QFS_EDEVICE, "qfs_height: device");
+    const GraphKey key{dev, batch, bound, max_p, band ? 1 : 0, p, f, heights, ws, ws_bytes};
+    std::lock_guard<std::mutex> lk(g_graphs.m);
+    for (GraphEntry &en : g_graphs.v)
+        if (en.key == key) {
+            en.used = ++g_graphs.tick;
+            const hipError_t e = hipGraphLaunch(en.exec, stream);
+            return e == hipSuccess ? QFS_OK : hip_fail(e, "graph launch");
+        }
+    bool again = false;
+    for (size_t i = 0; i < g_graphs.seen.size() && !again; ++i)
+        if (g_graphs.seen[i] == key) {
+            g_graphs.seen.erase(g_graphs.seen.begin() + i);
+            again = true;
+        }
+    if (!again) {  // first time: launch directly and remember the arguments
+        if (g_graphs.seen.size() >= 2 * GRAPH_CACHE) g_graphs.seen.erase(g_graphs.seen.begin());
+        g_graphs.seen.push_back(key);
+        return enqueue_height(batch, p, f, bound, L, heights, (uint8_t *)ws, band, gwg, stream, prof);
+    }
+    hipError_t e;
+    if (!g_graphs.cap[dev] && (e = hipStreamCreateWithFlags(&g_graphs.cap[dev], hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "capture stream");
+    hipStream_t cs = g_graphs.cap[dev];
+    if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) return hip_fail(e, "capture");
+    const int rc = enqueue_height(batch, p, f, bound, L, heights, (uint8_t *)ws, band, gwg, cs, prof);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    if (rc != QFS_OK || e != hipSuccess) {
+        if (graph) hipGraphDestroy(graph);
+        return rc != QFS_OK ? rc : hip_fail(e, "end capture");
+    }
+    hipGraphExec_t exec = nullptr;
+    if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+        hipGraphDestroy(graph);
+        return hip_fail(e, "graph instantiate");
+    }
+    if (g_graphs.v.size() >= GRAPH_CACHE) {
+        // evict the least recently used graph; its last launch must have finished
+        size_t lru = 0;
+        for (size_t i = 1; i < g_graphs.v.size(); ++i)
+            if (g_graphs.v[i].used < g_graphs.v[lru].used) lru = i;
+        hipDeviceSynchronize();
+        destroy_entry(g_graphs.v[lru]);
+        g_graphs.v.erase(g_graphs.v.begin() + lru);
+    }
+    g_graphs.v.push_back({key, graph, exec, ++g_graphs.tick});
+    e = hipGraphLaunch(exec, stream);
+    return e == hipSuccess ? QFS_OK : hip_fail(e, "graph launch");
 }
 
 int qfs_profile_enable(int on)
@@ -371,12 +480,22 @@ int qfs_set_option(const char *name, int64_t value)
         g_opt_height_band.store(value != 0);
         return QFS_OK;
     }
+    if (std::strcmp(name, "height_graph") == 0) {
+        if (value != 0 && value != 1) return fail(QFS_EINVAL, "qfs_set_option: height_graph must be 0 or 1");
+        g_opt_height_graph.store(value != 0);
+        return QFS_OK;
+    }
     return fail(QFS_EINVAL, "qfs_set_option: unknown option '%s'", name);
 }
 
 int64_t qfs_get_option(const char *name)
 {
     if (name && std::strcmp(name, "height_band") == 0) return g_opt_height_band.load() ? 1 : 0;
+    if (name && std::strcmp(name, "height_graph") == 0) return g_opt_height_graph.load() ? 1 : 0;
+    if (name && std::strcmp(name, "height_graphs_cached") == 0) {
+        std::lock_guard<std::mutex> lk(g_graphs.m);
+        return (int64_t)g_graphs.v.size();
+    }
     return fail(QFS_EINVAL, "qfs_get_option: unknown option");
 }
 

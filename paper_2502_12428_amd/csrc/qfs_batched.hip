@@ -773,14 +773,35 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
     }
 }
 
+// LDS limit of the deep kernels, set once per process (before any launch, so
+// also before a graph capture)
+template <int P, bool BAND>
+static hipError_t deep_attr()
+{
+    static const hipError_t attr = hipFuncSetAttribute((const void *)k_deep<P, BAND>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)DeepLds<P>::bytes);
+    return attr;
+}
+
+hipError_t prepare_deep(int p)
+{
+    hipError_t e = hipErrorInvalidValue;
+    switch (p) {
+    case 3: e = deep_attr<3, true>(); return e != hipSuccess ? e : deep_attr<3, false>();
+    case 5: e = deep_attr<5, true>(); return e != hipSuccess ? e : deep_attr<5, false>();
+    case 7: e = deep_attr<7, true>(); return e != hipSuccess ? e : deep_attr<7, false>();
+    case 11: e = deep_attr<11, true>(); return e != hipSuccess ? e : deep_attr<11, false>();
+    }
+    return e;
+}
+
 template <int P, bool BAND>
 static hipError_t launch_deep_pb(const DeepArgs &a, int nslots, hipStream_t s)
 {
-    const size_t lds = DeepLds<P>::bytes;
-    static const hipError_t attr =
-        hipFuncSetAttribute((const void *)k_deep<P, BAND>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t attr = deep_attr<P, BAND>();
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_deep<P, BAND>), dim3(nslots), dim3(DEEP_NT), lds, s, a);
+    hipLaunchKernelGGL((k_deep<P, BAND>), dim3(nslots), dim3(DEEP_NT), DeepLds<P>::bytes, s, a);
     return hipGetLastError();
 }
 

@@ -315,6 +315,8 @@ hipError_t launch_gpow(int p, const Stage1Args &a, int nwg, hipStream_t s);
 hipError_t launch_plan(int p, uint32_t *plan, hipStream_t s);
 // band: the capped-chain kernel (MODE_HEIGHT), else the full-chain kernel
 hipError_t launch_deep(int p, bool band, const DeepArgs &a, int nslots, hipStream_t s);
+// set the deep kernels' launch attributes for prime p (idempotent)
+hipError_t prepare_deep(int p);
 
 // theta on caller-given Delta (CNS order): converts Delta into the
 // Cartier-split layout, then iterates.

@@ -109,3 +109,10 @@ def test_options():
         qfs.set_option("no_such_option", 1)
     with pytest.raises(qfs.QfsError):
         qfs.get_option("no_such_option")
+    assert qfs.get_option("height_graph") == 1
+    qfs.set_option("height_graph", 0)
+    try:
+        assert qfs.get_option("height_graph") == 0
+    finally:
+        qfs.set_option("height_graph", 1)
+    assert qfs.get_option("height_graphs_cached") == 0

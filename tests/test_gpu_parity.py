@@ -247,3 +247,32 @@ def test_height_bound_two_on_workloads(qfs, name):
     say("height bound 2: %s" % name)
     got = host(qfs.height(dev(F), dev(P), bound=2, max_p=int(P.max())))
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("name", ["p5_batch8192", "mixed4096"])
+def test_height_graph_replays_match_direct_launches(qfs, name):
+    # the second call with the same arguments captures the launch sequence into
+    # a hipGraph; later calls replay it.  Between replays the program does its
+    # own eager GPU work and synchronizes; every replay must equal the direct result.
+    F, P, H = load_golden(name)
+    f, pt = dev(F), dev(P)
+    maxp = int(P.max())
+    ws = qfs.Workspace()
+    out = torch.empty(len(H), dtype=torch.int32, device="cuda")
+    say("height graph replays: %s" % name)
+    qfs.set_option("height_graph", 0)
+    try:
+        direct = host(qfs.height(f, pt, max_p=maxp, workspace=ws, out=out)).copy()
+    finally:
+        qfs.set_option("height_graph", 1)
+    assert np.array_equal(direct, H)
+    before = qfs.get_option("height_graphs_cached")
+    for rep in range(5):
+        out.fill_(-7)
+        got = host(qfs.height(f, pt, max_p=maxp, workspace=ws, out=out)).copy()
+        assert np.array_equal(got, direct), "replay %d differs" % rep
+        # unrelated eager work on the same stream between replays
+        x = torch.randn(512, 512, device="cuda")
+        (x @ x).sum().item()
+        torch.cuda.synchronize()
+    assert qfs.get_option("height_graphs_cached") >= min(before + 1, 8)

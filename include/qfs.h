@@ -175,6 +175,9 @@ int64_t qfs_mfma_per_surface(int p, int pass);
  *   "height_graph" (default 1): replay cached hipGraphs of the qfs_height
  *     launch sequence (see qfs_height); 0 launches the kernels directly.
  *   "height_graphs_cached" (read only): number of graphs in the cache.
+ *   "deep_slots" (default 0 = one per compute unit): persistent workgroups
+ *     of the deep kernels, each with its own slot of workspace; it changes
+ *     the *_workspace_bytes results, so query them after setting it.
  * qfs_set_option returns QFS_OK or QFS_EINVAL (unknown name or value);
  * qfs_get_option returns the value, or QFS_EINVAL for an unknown name. */
 int qfs_set_option(const char *name, int64_t value);

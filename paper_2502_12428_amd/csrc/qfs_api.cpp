@@ -21,6 +21,7 @@ thread_local char g_err[512] = "";
 // process-wide options (qfs_set_option)
 std::atomic<bool> g_opt_height_band{true};
 std::atomic<bool> g_opt_height_graph{true};
+std::atomic<int> g_opt_deep_slots{0};  // persistent deep workgroups; 0 = one per compute unit
 
 int fail(int code, const char *fmt, ...)
 {
@@ -43,6 +44,12 @@ int device_cus()
 }
 
 bool aligned(const void *p) { return ((uintptr_t)p & 255u) == 0; }
+
+int deep_slots()
+{
+    const int v = g_opt_deep_slots.load();
+    return v > 0 ? v : device_cus();
+}
 
 // persistent workgroups of the g = f^(p-1) kernel: a few per compute unit
 int gpow_workgroups(int batch)
@@ -196,7 +203,7 @@ size_t qfs_delta1_workspace_bytes(int p, int batch)
     if (!supported(p) || batch < 0) return 0;
     bool present[4] = {false, false, false, false};
     present[prime_index(p)] = true;
-    return make_batch_layout(present, batch, device_cus()).total;
+    return make_batch_layout(present, batch, deep_slots()).total;
 }
 
 int qfs_delta1(int p, int batch, const uint8_t *f, uint8_t *g_out, uint8_t *delta_out, int32_t *status_out,
@@ -213,7 +220,7 @@ int qfs_delta1(int p, int batch, const uint8_t *f, uint8_t *g_out, uint8_t *delt
     bool present[4] = {false, false, false, false};
     const int pi = prime_index(p);
     present[pi] = true;
-    const BatchLayout L = make_batch_layout(present, batch, ncu);
+    const BatchLayout L = make_batch_layout(present, batch, deep_slots());
     if (ws_bytes < L.total)
         return fail(QFS_ENOMEM, "qfs_delta1: workspace %zu bytes < %zu needed", ws_bytes, L.total);
     uint8_t *w = (uint8_t *)ws;
@@ -295,7 +302,7 @@ size_t qfs_height_workspace_bytes(int batch, int max_p)
     if (batch < 0 || max_p < 3 || max_p > 11) return 0;
     bool present[4];
     present_upto(max_p, present);
-    return make_batch_layout(present, batch, device_cus()).total;
+    return make_batch_layout(present, batch, deep_slots()).total;
 }
 
 // The launch sequence of qfs_height on `stream` (validated arguments).
@@ -373,7 +380,7 @@ int qfs_height(int batch, const int32_t *p, const uint8_t *f, int bound, int max
     if (ncu <= 0) return fail(QFS_EDEVICE, "qfs_height: no HIP device");
     bool present[4];
     present_upto(max_p, present);
-    const BatchLayout L = make_batch_layout(present, batch, ncu);
+    const BatchLayout L = make_batch_layout(present, batch, deep_slots());
     if (ws_bytes < L.total)
         return fail(QFS_ENOMEM, "qfs_height: workspace %zu bytes < %zu needed", ws_bytes, L.total);
     const bool band = g_opt_height_band.load() && bound >= 2;
@@ -485,6 +492,11 @@ int qfs_set_option(const char *name, int64_t value)
         g_opt_height_graph.store(value != 0);
         return QFS_OK;
     }
+    if (std::strcmp(name, "deep_slots") == 0) {
+        if (value < 0 || value > 65536) return fail(QFS_EINVAL, "qfs_set_option: deep_slots must be 0..65536");
+        g_opt_deep_slots.store((int)value);
+        return QFS_OK;
+    }
     return fail(QFS_EINVAL, "qfs_set_option: unknown option '%s'", name);
 }
 
@@ -492,6 +504,7 @@ int64_t qfs_get_option(const char *name)
 {
     if (name && std::strcmp(name, "height_band") == 0) return g_opt_height_band.load() ? 1 : 0;
     if (name && std::strcmp(name, "height_graph") == 0) return g_opt_height_graph.load() ? 1 : 0;
+    if (name && std::strcmp(name, "deep_slots") == 0) return g_opt_deep_slots.load();
     if (name && std::strcmp(name, "height_graphs_cached") == 0) {
         std::lock_guard<std::mutex> lk(g_graphs.m);
         return (int64_t)g_graphs.v.size();

@@ -920,14 +920,9 @@ static size_t plan_bytes_of(int p)
 }
 
 // Persistent workgroups per compute unit for p <= 7 (QFS_DEEP_WGS_PER_CU, 1..8; default 1).
-static int deep_wgs_per_cu()
-{
-    const char *e = getenv("QFS_DEEP_WGS_PER_CU");
-    int v = e ? atoi(e) : 1;
-    return v < 1 ? 1 : v > 8 ? 8 : v;
-}
+constexpr size_t SLOT_AREA_MAX = (size_t)96 << 30;
 
-BatchLayout make_batch_layout(const bool present[4], int batch, int n_cu)
+BatchLayout make_batch_layout(const bool present[4], int batch, int slots)
 {
     BatchLayout L;
     size_t off = align256(CNT_WORDS * sizeof(int32_t));
@@ -943,8 +938,11 @@ BatchLayout make_batch_layout(const bool present[4], int batch, int n_cu)
         off += align256((size_t)batch * (size_t)len_g_of(p));
         L.plan[i] = off;
         off += align256(plan_bytes_of(p));
-        // one persistent workgroup per compute unit; p = 11 boxes are large, so fewer
-        int ns = p == 11 ? (n_cu < 64 ? n_cu : 64) : n_cu * deep_wgs_per_cu();
+        // `slots` persistent workgroups (one per compute unit by default), the
+        // slot area held to SLOT_AREA_MAX (a p = 11 slot is 242 MB)
+        int ns = slots;
+        const size_t cap = SLOT_AREA_MAX / slot_bytes_of(p);
+        if ((size_t)ns > cap) ns = (int)cap;
         if (ns > batch) ns = batch;
         L.nslots[i] = ns > 0 ? ns : 1;
         L.slot_stride[i] = slot_bytes_of(p);

@@ -268,9 +268,9 @@ struct BatchLayout {
     size_t total = 0;
 };
 
-// Layout for the primes marked in `present`, `batch` surfaces and the given
-// number of compute units.
-BatchLayout make_batch_layout(const bool present[4], int batch, int n_cu);
+// Layout for the primes marked in `present`, `batch` surfaces and up to
+// `slots` persistent deep workgroups.
+BatchLayout make_batch_layout(const bool present[4], int batch, int slots);
 
 int64_t len_g_of(int p);
 

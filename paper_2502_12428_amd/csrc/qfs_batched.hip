@@ -308,13 +308,18 @@ __device__ void build_w(const uint8_t *g, uint8_t *W)
         if (v < X::NV) {
             const uint32_t dl = kDX<P>.vpacked[v];
             const int b1 = T1 * unp0(dl) + s1, b2 = T2 * unp1(dl) + s2, b3 = T3 * unp2(dl) + s3;
+            // 16 unconditional LDS reads (outside the simplex: index 0, masked after)
+            unsigned val[16];
+#pragma unroll
             for (int sp = 0; sp < 16; ++sp) {
                 const int x1 = b1 - (sp >> 3), x2 = b2 - ((sp >> 2) & 1), x3 = b3 - (sp & 3);
                 const int x4 = d - x1 - x2 - x3;
-                unsigned val = 0;
-                if (x1 >= 0 && x2 >= 0 && x3 >= 0 && x4 >= 0) val = g[cns_rank(x2, x3, x4)];
-                w[sp >> 2] |= val << (8 * (sp & 3));
+                const bool in = x1 >= 0 && x2 >= 0 && x3 >= 0 && x4 >= 0;
+                val[sp] = g[in ? cns_rank(x2, x3, x4) : 0];
+                if (!in) val[sp] = 0;
             }
+#pragma unroll
+            for (int sp = 0; sp < 16; ++sp) w[sp >> 2] |= val[sp] << (8 * (sp & 3));
         }
         *(v4u *)(W + (size_t)row * 16) = v4u{w[0], w[1], w[2], w[3]};
     }
@@ -330,11 +335,16 @@ __device__ void init_a1(const uint8_t *g, const uint32_t *list, int ntiles, uint
         const int c1 = unp0(t), c2 = unp1(t), c3 = unp2(t);
         unsigned w[4] = {0, 0, 0, 0};
         if (T1 * c1 + T2 * c2 + T3 * c3 <= d) {
+            unsigned val[16];
+#pragma unroll
             for (int s = 0; s < 16; ++s) {
                 const int x1 = T1 * c1 + (s >> 3), x2 = T2 * c2 + ((s >> 2) & 1), x3 = T3 * c3 + (s & 3);
                 const int x4 = d - x1 - x2 - x3;
-                if (x4 >= 0) w[s >> 2] |= (unsigned)g[cns_rank(x2, x3, x4)] << (8 * (s & 3));
+                val[s] = g[x4 >= 0 ? cns_rank(x2, x3, x4) : 0];
+                if (x4 < 0) val[s] = 0;
             }
+#pragma unroll
+            for (int s = 0; s < 16; ++s) w[s >> 2] |= val[s] << (8 * (s & 3));
         }
         gstore16(A + box_tile<P>(c1, c2, c3) * 16, v4u{w[0], w[1], w[2], w[3]});
     }
@@ -484,18 +494,27 @@ __device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *l
 #pragma unroll
     for (int b = 0; b < NB; ++b) boff[b] = (uint32_t)base[b] * 16u;
     const uint32_t wrow = (uint32_t)col * 16u;
-    // Software pipeline over the list.  Slot j holds the input fragments of one
-    // entry (loaded DEEP_PF entries ahead) with that entry's packed W-block
-    // indices; the W fragments of the next entry are read from LDS while the
-    // current entry's products issue, so no LDS round trip sits right before
-    // the matrix instructions.
-    // slot J <- list entry I (clamped to the last entry): W indices and input fragments
-#define QFS_LOAD_B(J, I)                                                                           \
+    // Software pipeline over the list.  For list entry e the steps are, each
+    // one loop step before the next: read its quad index; read its tile offset
+    // and packed W-block indices; issue its input-fragment loads into slot
+    // e mod DEEP_PF (DEEP_PF entries ahead of its products); read its W
+    // fragments from LDS; issue its 4 x NB products.  So no LDS round trip
+    // sits right before the matrix instructions.  Entries past the end
+    // repeat the last one (the list is padded with null quads).
+#define QFS_ENTRY(I) ((I) < nq ? (I) : nq - 1)
+    // index data of entry I from its quad q
+#define QFS_INDEX(Q)                                                                               \
     do {                                                                                           \
-        const int q_ = uniform(qlist[(I) < nq ? (I) : nq - 1]);                                    \
-        const uint32_t to_ = (uint32_t)toff_l[4 * q_ + kg] * 16u;                                  \
-        wa[J] = widx_l[2 * (4 * q_ + kg)];                                                         \
-        wb[J] = widx_l[2 * (4 * q_ + kg) + 1];                                                     \
+        tn = toff_l[4 * (Q) + kg];                                                                 \
+        wan = widx_l[2 * (4 * (Q) + kg)];                                                          \
+        wbn = widx_l[2 * (4 * (Q) + kg) + 1];                                                      \
+    } while (0)
+    // slot J <- the staged entry: W indices and input fragments
+#define QFS_LOAD_B(J)                                                                              \
+    do {                                                                                           \
+        const uint32_t to_ = (uint32_t)tn * 16u;                                                   \
+        wa[J] = wan;                                                                               \
+        wb[J] = wbn;                                                                               \
         _Pragma("unroll") for (int b = 0; b < NB; ++b) bf[J][b] = gload16(Ain + (boff[b] - to_));  \
     } while (0)
     // W fragments (four shifts) of the entry in slot J into buffer K
@@ -519,14 +538,20 @@ __device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *l
     if (nq > 0) {
         v4i bf[DEEP_PF][NB], wf[2][4];
         uint32_t wa[DEEP_PF], wb[DEEP_PF];
+        int tn;
+        uint32_t wan, wbn;
 #pragma unroll
         for (int j = 0; j < DEEP_PF; ++j) {
-            QFS_LOAD_B(j, j);
+            QFS_INDEX(uniform(qlist[QFS_ENTRY(j)]));
+            QFS_LOAD_B(j);
             __builtin_amdgcn_sched_barrier(0);
         }
         QFS_LOAD_W(0, 0);
+        QFS_INDEX(uniform(qlist[QFS_ENTRY(DEEP_PF)]));
+        int qv = qlist[QFS_ENTRY(DEEP_PF + 1)];
         __builtin_amdgcn_sched_barrier(0);
-        // at the top of an iteration slot j holds entry i + j
+        // at the top of an iteration slot j holds entry i + j, the staged index
+        // data is entry i + DEEP_PF's and qv holds entry i + DEEP_PF + 1's quad
         for (int i = 0; i < nq; i += DEEP_PF) {
 #pragma unroll
             for (int j = 0; j < DEEP_PF; ++j) {
@@ -534,11 +559,16 @@ __device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *l
                 __builtin_amdgcn_sched_barrier(0);
                 QFS_PRODUCTS(j & 1, j);
                 __builtin_amdgcn_sched_barrier(0);
-                QFS_LOAD_B(j, i + j + DEEP_PF);
+                QFS_LOAD_B(j);
+                const int q_ = uniform(qv);
+                qv = qlist[QFS_ENTRY(i + j + DEEP_PF + 2)];
+                QFS_INDEX(q_);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
+#undef QFS_ENTRY
+#undef QFS_INDEX
 #undef QFS_LOAD_B
 #undef QFS_LOAD_W
 #undef QFS_PRODUCTS

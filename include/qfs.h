@@ -137,6 +137,27 @@ int qfs_height(int batch, const int32_t *p, const uint8_t *f, int bound, int max
                void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * qfs_autotune -- times qfs_height on the caller's batch (arguments as for
+ * qfs_height) over a grid of launch settings: "deep_slots" in {CUs/2,
+ * 3 CUs/4, CUs} x "gpow_per_cu" in {4, 8, 16}, each after one warm-up call,
+ * `reps` (1..100) timed calls, direct launches (no graphs).  It keeps the
+ * fastest setting as the process-wide options and, if cache_path is not
+ * NULL, appends one JSON line (device architecture, compute units, max_p,
+ * batch, the chosen options, the mean milliseconds of every trial) to that
+ * file.  `ws` must hold qfs_height_workspace_bytes(batch, max_p) with one
+ * slot per compute unit.  heights receives the last trial's output.
+ * Synchronizes `stream`.  Returns QFS_OK or a negative qfs_status (options
+ * unchanged on error).
+ *
+ * qfs_load_tuning -- applies the last line of cache_path written by
+ * qfs_autotune for this device architecture, compute-unit count and max_p.
+ * Returns QFS_OK, or QFS_EINVAL if the file cannot be read or has no such line.
+ * ---------------------------------------------------------------------- */
+int qfs_autotune(int batch, const int32_t *p, const uint8_t *f, int bound, int max_p, int32_t *heights, void *ws,
+                 size_t ws_bytes, hipStream_t stream, const char *cache_path, int reps);
+int qfs_load_tuning(const char *cache_path, int max_p);
+
+/* ------------------------------------------------------------------------
  * qfs_height_plain -- the same heights for surfaces of one prime p, computed
  * one surface at a time with plain vector-ALU kernels (no matrix cores, no
  * batching): the comparison baseline for qfs_height.  Arguments as above.
@@ -178,6 +199,8 @@ int64_t qfs_mfma_per_surface(int p, int pass);
  *   "deep_slots" (default 0 = one per compute unit): persistent workgroups
  *     of the deep kernels, each with its own slot of workspace; it changes
  *     the *_workspace_bytes results, so query them after setting it.
+ *   "gpow_per_cu" (default 8, 1..64): workgroups per compute unit of the
+ *     kernel that forms g = f^(p-1) for the deep surfaces.
  * qfs_set_option returns QFS_OK or QFS_EINVAL (unknown name or value);
  * qfs_get_option returns the value, or QFS_EINVAL for an unknown name. */
 int qfs_set_option(const char *name, int64_t value);

@@ -35,7 +35,7 @@ EXPORTS = (
     "qfs_delta1_workspace_bytes", "qfs_delta1", "qfs_theta_workspace_bytes", "qfs_theta",
     "qfs_height_workspace_bytes", "qfs_height", "qfs_height_plain_workspace_bytes", "qfs_height_plain",
     "qfs_profile_enable", "qfs_profile_collect", "qfs_mfma_per_surface", "qfs_set_option", "qfs_get_option",
-    "qfs_last_error", "qfs_shutdown",
+    "qfs_autotune", "qfs_load_tuning", "qfs_last_error", "qfs_shutdown",
 )
 
 
@@ -76,6 +76,8 @@ def lib():
     L.qfs_mfma_per_surface.argtypes, L.qfs_mfma_per_surface.restype = [i32, i32], i64
     L.qfs_set_option.argtypes, L.qfs_set_option.restype = [ctypes.c_char_p, i64], i32
     L.qfs_get_option.argtypes, L.qfs_get_option.restype = [ctypes.c_char_p], i64
+    L.qfs_autotune.argtypes, L.qfs_autotune.restype = [i32, vp, vp, i32, i32, vp, vp, sz, vp, ctypes.c_char_p, i32], i32
+    L.qfs_load_tuning.argtypes, L.qfs_load_tuning.restype = [ctypes.c_char_p, i32], i32
     L.qfs_last_error.argtypes, L.qfs_last_error.restype = [], ctypes.c_char_p
     L.qfs_shutdown.argtypes, L.qfs_shutdown.restype = [], None
     _lib = L
@@ -193,6 +195,33 @@ def height(f, p, bound=10, max_p=None, workspace=None, out=None):
     _check(lib().qfs_height(B, _ptr(pt), _ptr(f), int(bound), int(max_p), _ptr(h), _ptr(ws), ws.numel(),
                             _stream()))
     return h
+
+
+def autotune(f, p, bound=10, max_p=None, workspace=None, cache_path=None, reps=2):
+    """Time qfs_height on this batch over the launch-setting grid, keep the fastest setting
+    (and append it to cache_path); returns the heights of the last trial."""
+    f = _device_u8(f, "f")
+    B = f.shape[0]
+    pt = p.to(device=f.device, dtype=torch.int32).contiguous() if isinstance(p, torch.Tensor) else \
+        torch.full((B,), int(p), dtype=torch.int32, device=f.device)
+    max_p = int(max_p or (int(pt.max().item()) if B else 3))
+    h = torch.empty(B, dtype=torch.int32, device=f.device)
+    slots = get_option("deep_slots")
+    set_option("deep_slots", 0)
+    try:
+        nbytes = lib().qfs_height_workspace_bytes(B, max_p)
+    finally:
+        set_option("deep_slots", slots)
+    ws = (workspace or _ws).get(nbytes, f.device)
+    path = cache_path.encode() if cache_path else None
+    _check(lib().qfs_autotune(B, _ptr(pt), _ptr(f), int(bound), max_p, _ptr(h), _ptr(ws), ws.numel(), _stream(),
+                              path, int(reps)))
+    return h
+
+
+def load_tuning(cache_path, max_p):
+    """Apply the settings qfs_autotune stored for this device and max_p."""
+    _check(lib().qfs_load_tuning(cache_path.encode(), int(max_p)))
 
 
 def height_plain(f, p, bound=10, workspace=None):

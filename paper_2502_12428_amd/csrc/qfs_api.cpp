@@ -22,6 +22,7 @@ thread_local char g_err[512] = "";
 std::atomic<bool> g_opt_height_band{true};
 std::atomic<bool> g_opt_height_graph{true};
 std::atomic<int> g_opt_deep_slots{0};  // persistent deep workgroups; 0 = one per compute unit
+std::atomic<int> g_opt_gpow_per_cu{8};  // workgroups per compute unit of the g = f^(p-1) kernel
 
 int fail(int code, const char *fmt, ...)
 {
@@ -54,7 +55,7 @@ int deep_slots()
 // persistent workgroups of the g = f^(p-1) kernel: a few per compute unit
 int gpow_workgroups(int batch)
 {
-    const int n = 8 * device_cus();
+    const int n = g_opt_gpow_per_cu.load() * device_cus();
     return batch < n ? batch : n;
 }
 
@@ -121,13 +122,14 @@ int hip_fail(hipError_t e, const char *what)
 
 // ---- graphs of the qfs_height launch sequence, keyed by every argument ----
 struct GraphKey {
-    int dev, batch, bound, max_p, band;
+    int dev, batch, bound, max_p, band, slots, gwg;
     const void *p, *f, *h, *ws;
     size_t ws_bytes;
     bool operator==(const GraphKey &o) const
     {
         return dev == o.dev && batch == o.batch && bound == o.bound && max_p == o.max_p && band == o.band &&
-               p == o.p && f == o.f && h == o.h && ws == o.ws && ws_bytes == o.ws_bytes;
+               slots == o.slots && gwg == o.gwg && p == o.p && f == o.f && h == o.h && ws == o.ws &&
+               ws_bytes == o.ws_bytes;
     }
 };
 struct GraphEntry {
@@ -396,7 +398,7 @@ int qfs_height(int batch, const int32_t *p, const uint8_t *f, int bound, int max
     // replay the graph of this exact call, or capture it on a library stream first
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEV) return fail(QFS_EDEVICE, "qfs_height: device");
-    const GraphKey key{dev, batch, bound, max_p, band ? 1 : 0, p, f, heights, ws, ws_bytes};
+    const GraphKey key{dev, batch, bound, max_p, band ? 1 : 0, deep_slots(), gwg, p, f, heights, ws, ws_bytes};
     std::lock_guard<std::mutex> lk(g_graphs.m);
     for (GraphEntry &en : g_graphs.v)
         if (en.key == key) {
@@ -497,6 +499,11 @@ int qfs_set_option(const char *name, int64_t value)
         g_opt_deep_slots.store((int)value);
         return QFS_OK;
     }
+    if (std::strcmp(name, "gpow_per_cu") == 0) {
+        if (value < 1 || value > 64) return fail(QFS_EINVAL, "qfs_set_option: gpow_per_cu must be 1..64");
+        g_opt_gpow_per_cu.store((int)value);
+        return QFS_OK;
+    }
     return fail(QFS_EINVAL, "qfs_set_option: unknown option '%s'", name);
 }
 
@@ -505,11 +512,126 @@ int64_t qfs_get_option(const char *name)
     if (name && std::strcmp(name, "height_band") == 0) return g_opt_height_band.load() ? 1 : 0;
     if (name && std::strcmp(name, "height_graph") == 0) return g_opt_height_graph.load() ? 1 : 0;
     if (name && std::strcmp(name, "deep_slots") == 0) return g_opt_deep_slots.load();
+    if (name && std::strcmp(name, "gpow_per_cu") == 0) return g_opt_gpow_per_cu.load();
     if (name && std::strcmp(name, "height_graphs_cached") == 0) {
         std::lock_guard<std::mutex> lk(g_graphs.m);
         return (int64_t)g_graphs.v.size();
     }
     return fail(QFS_EINVAL, "qfs_get_option: unknown option");
+}
+
+// ---------------------------------------------------------------------------
+// Launch-configuration autotuner for qfs_height.
+// ---------------------------------------------------------------------------
+static void device_name(char *out, size_t n)
+{
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        std::snprintf(out, n, "unknown");
+        return;
+    }
+    std::snprintf(out, n, "%s", prop.gcnArchName);
+    for (char *c = out; *c; ++c)
+        if (*c == '"' || *c == '\\') *c = '_';
+}
+
+int qfs_autotune(int batch, const int32_t *p, const uint8_t *f, int bound, int max_p, int32_t *heights, void *ws,
+                 size_t ws_bytes, hipStream_t stream, const char *cache_path, int reps)
+{
+    g_err[0] = 0;
+    if (batch <= 0) return fail(QFS_EINVAL, "qfs_autotune: batch=%d must be positive", batch);
+    if (reps < 1 || reps > 100) return fail(QFS_EINVAL, "qfs_autotune: reps=%d outside 1..100", reps);
+    const int ncu = device_cus();
+    if (ncu <= 0) return fail(QFS_EDEVICE, "qfs_autotune: no HIP device");
+    if (max_p < 3 || max_p > 11 || !supported(max_p))
+        return fail(QFS_EUNSUPPORTED, "qfs_autotune: max_p=%d not in {3,5,7,11}", max_p);
+    {
+        bool present[4];
+        present_upto(max_p, present);
+        if (ws_bytes < make_batch_layout(present, batch, ncu).total)
+            return fail(QFS_ENOMEM, "qfs_autotune: workspace smaller than qfs_height needs with one slot per CU");
+    }
+    const int slots_save = g_opt_deep_slots.load(), gpow_save = g_opt_gpow_per_cu.load();
+    const bool graph_save = g_opt_height_graph.load();
+    g_opt_height_graph.store(false);  // time direct launches
+    const int slot_c[3] = {ncu / 2, (3 * ncu) / 4, ncu};
+    const int gpow_c[3] = {4, 8, 16};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = QFS_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(QFS_EDEVICE, "qfs_autotune: events");
+    float best = 1e30f, trial[9];
+    int bs = ncu, bg = 8;
+    for (int i = 0; i < 9 && rc == QFS_OK; ++i) {
+        g_opt_deep_slots.store(slot_c[i / 3] > 0 ? slot_c[i / 3] : 1);
+        g_opt_gpow_per_cu.store(gpow_c[i % 3]);
+        rc = qfs_height(batch, p, f, bound, max_p, heights, ws, ws_bytes, stream);  // warm-up
+        if (rc != QFS_OK) break;
+        hipEventRecord(e0, stream);
+        for (int r = 0; r < reps && rc == QFS_OK; ++r) rc = qfs_height(batch, p, f, bound, max_p, heights, ws, ws_bytes, stream);
+        hipEventRecord(e1, stream);
+        if (hipEventSynchronize(e1) != hipSuccess) rc = fail(QFS_EDEVICE, "qfs_autotune: event wait");
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        trial[i] = ms / reps;
+        if (rc == QFS_OK && trial[i] < best) {
+            best = trial[i];
+            bs = g_opt_deep_slots.load();
+            bg = g_opt_gpow_per_cu.load();
+        }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    g_opt_height_graph.store(graph_save);
+    if (rc != QFS_OK) {
+        g_opt_deep_slots.store(slots_save);
+        g_opt_gpow_per_cu.store(gpow_save);
+        return rc;
+    }
+    g_opt_deep_slots.store(bs == ncu ? 0 : bs);
+    g_opt_gpow_per_cu.store(bg);
+    if (cache_path) {
+        FILE *fp = std::fopen(cache_path, "a");
+        if (!fp) return fail(QFS_EINVAL, "qfs_autotune: cannot append to %s", cache_path);
+        char name[128];
+        device_name(name, sizeof name);
+        std::fprintf(fp, "{\"device\": \"%s\", \"cus\": %d, \"max_p\": %d, \"batch\": %d, \"deep_slots\": %d, "
+                         "\"gpow_per_cu\": %d, \"ms\": %.4f, \"trials_ms\": [",
+                     name, ncu, max_p, batch, bs == ncu ? 0 : bs, bg, best);
+        for (int i = 0; i < 9; ++i) std::fprintf(fp, "%s%.4f", i ? ", " : "", trial[i]);
+        std::fprintf(fp, "]}\n");
+        std::fclose(fp);
+    }
+    return QFS_OK;
+}
+
+int qfs_load_tuning(const char *cache_path, int max_p)
+{
+    g_err[0] = 0;
+    if (!cache_path) return fail(QFS_EINVAL, "qfs_load_tuning: null path");
+    FILE *fp = std::fopen(cache_path, "r");
+    if (!fp) return fail(QFS_EINVAL, "qfs_load_tuning: cannot read %s", cache_path);
+    char name[128], line[1024];
+    device_name(name, sizeof name);
+    const int ncu = device_cus();
+    int found = 0, slots = 0, gpow = 8;
+    while (std::fgets(line, sizeof line, fp)) {
+        char dev[128] = "";
+        int cus = 0, mp = 0, b = 0, ds = 0, gp = 0;
+        if (std::sscanf(line, "{\"device\": \"%127[^\"]\", \"cus\": %d, \"max_p\": %d, \"batch\": %d, \"deep_slots\": %d, "
+                              "\"gpow_per_cu\": %d",
+                        dev, &cus, &mp, &b, &ds, &gp) == 6 &&
+            std::strcmp(dev, name) == 0 && cus == ncu && mp == max_p && ds >= 0 && gp >= 1 && gp <= 64) {
+            found = 1;  // the last matching line wins
+            slots = ds;
+            gpow = gp;
+        }
+    }
+    std::fclose(fp);
+    if (!found) return fail(QFS_EINVAL, "qfs_load_tuning: no entry for this device and max_p=%d", max_p);
+    g_opt_deep_slots.store(slots);
+    g_opt_gpow_per_cu.store(gpow);
+    return QFS_OK;
 }
 
 // ---------------------------------------------------------------------------

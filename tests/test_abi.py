@@ -116,3 +116,14 @@ def test_options():
     finally:
         qfs.set_option("height_graph", 1)
     assert qfs.get_option("height_graphs_cached") == 0
+
+
+def test_autotune_and_tuning_cache_argument_errors(tmp_path):
+    L = qfs.lib()
+    assert L.qfs_autotune(0, None, None, 10, 7, None, None, 0, None, None, 2) == qfs.QFS_EINVAL
+    assert L.qfs_autotune(4, None, None, 10, 7, None, None, 0, None, None, 0) == qfs.QFS_EINVAL
+    assert L.qfs_load_tuning(None, 7) == qfs.QFS_EINVAL
+    assert L.qfs_load_tuning(str(tmp_path / "missing.jsonl").encode(), 7) == qfs.QFS_EINVAL
+    with pytest.raises(qfs.QfsError):
+        qfs.set_option("gpow_per_cu", 0)
+    assert qfs.get_option("gpow_per_cu") == 8

@@ -276,3 +276,27 @@ def test_height_graph_replays_match_direct_launches(qfs, name):
         (x @ x).sum().item()
         torch.cuda.synchronize()
     assert qfs.get_option("height_graphs_cached") >= min(before + 1, 8)
+
+
+def test_autotune_keeps_heights_and_stores_its_choice(qfs, tmp_path):
+    F, P, H = load_golden("p5_batch8192")
+    cache = str(tmp_path / "tune.jsonl")
+    say("autotune p5_batch8192")
+    try:
+        got = host(qfs.autotune(dev(F), dev(P), max_p=5, cache_path=cache, reps=1))
+        assert np.array_equal(got, H)
+        chosen = (qfs.get_option("deep_slots"), qfs.get_option("gpow_per_cu"))
+        lines = open(cache).read().strip().splitlines()
+        assert len(lines) == 1
+        rec = json.loads(lines[0])
+        assert (rec["deep_slots"], rec["gpow_per_cu"]) == chosen and len(rec["trials_ms"]) == 9
+        # heights under the chosen setting, and after reloading it from the file
+        assert np.array_equal(host(qfs.height(dev(F), dev(P), max_p=5)), H)
+        qfs.set_option("deep_slots", 0)
+        qfs.set_option("gpow_per_cu", 8)
+        qfs.load_tuning(cache, 5)
+        assert (qfs.get_option("deep_slots"), qfs.get_option("gpow_per_cu")) == chosen
+        assert np.array_equal(host(qfs.height(dev(F), dev(P), max_p=5)), H)
+    finally:
+        qfs.set_option("deep_slots", 0)
+        qfs.set_option("gpow_per_cu", 8)

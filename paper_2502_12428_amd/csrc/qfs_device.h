@@ -148,50 +148,63 @@ __device__ inline void build_aperm(const uint8_t *a_cns, uint8_t *aperm)
     }
 }
 
-// Delta in the Cartier-split layout dl (global), built by 16-byte chunks:
-// chunk m of row y in region j holds Delta[p y + sigma] for the region's
-// columns 16m .. 16m+15 (sigma from the column table, zero for padding).
-// src(x1, x2, x3, x4) returns Delta at a position of degree D.
+// Chunk ch (16 bytes) of Delta's Cartier-split layout, gathered through src.
 template <int P, class Src>
-__device__ inline void cartier_split(Src &&src, uint8_t *dl)
+__device__ __attribute__((always_inline)) inline v4u cartier_chunk(Src &src, int64_t ch)
 {
     using TG = ThetaGeo<P>;
     constexpr int d = TG::d;
-    constexpr int64_t NCH = TG::BYTES / 16;
-    for (int64_t ch = threadIdx.x; ch < NCH; ch += blockDim.x) {
-        int j = 0;
+    int j = 0;
 #pragma unroll
-        for (int i = 1; i < TG::J; ++i)
-            if (ch * 16 >= kTT<P>.roff[i]) j = i;
-        const int nc = kTT<P>.rs[j] / 16;
-        const int64_t local = ch - kTT<P>.roff[j] / 16;
-        const int y = (int)(local / nc), m = (int)(local % nc);
-        int y1, y2, y3, y4;
-        cns_unrank(d - j, y, y1, y2, y3, y4);
-        int cb = 0;
+    for (int i = 1; i < TG::J; ++i)
+        if (ch * 16 >= kTT<P>.roff[i]) j = i;
+    const int nc = kTT<P>.rs[j] / 16;
+    const int64_t local = ch - kTT<P>.roff[j] / 16;
+    const int y = (int)(local / nc), m = (int)(local % nc);
+    int y1, y2, y3, y4;
+    cns_unrank(d - j, y, y1, y2, y3, y4);
+    int cb = 0;
 #pragma unroll
-        for (int i = 1; i < TG::J; ++i)
-            if (j == i) cb = TG::col_off(i);
-        // the chunk's 16 columns (two 16-byte loads); column 16m is never padding
-        const v4u *sg = (const v4u *)(kTT<P>.sig + cb + 16 * m);
-        const v4u s0 = sg[0], s1 = sg[1];
-        const unsigned sw[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
-        const unsigned first = sw[0] & 0xFFFFu;
-        // all 16 loads are issued unconditionally (padding reads column 16m's position) and masked after
-        unsigned b[16];
+    for (int i = 1; i < TG::J; ++i)
+        if (j == i) cb = TG::col_off(i);
+    // the chunk's 16 columns (two 16-byte loads); column 16m is never padding
+    const v4u *sg = (const v4u *)(kTT<P>.sig + cb + 16 * m);
+    const v4u s0 = sg[0], s1 = sg[1];
+    const unsigned sw[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+    const unsigned first = sw[0] & 0xFFFFu;
+    // all 16 loads are issued unconditionally (padding reads column 16m's position) and masked after
+    unsigned b[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const unsigned raw = (sw[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
-            const unsigned s = raw == 0xFFFFu ? first : raw;
-            b[q] = src(P * y1 + (int)(s & 15), P * y2 + (int)((s >> 4) & 15), P * y3 + (int)((s >> 8) & 15),
-                       P * y4 + (int)(s >> 12));
-            if (raw == 0xFFFFu) b[q] = 0;
-        }
-        unsigned w[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int q = 0; q < 16; ++q) w[q >> 2] |= b[q] << (8 * (q & 3));
-        gstore16(dl + ch * 16, v4u{w[0], w[1], w[2], w[3]});
+    for (int q = 0; q < 16; ++q) {
+        const unsigned raw = (sw[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
+        const unsigned s = raw == 0xFFFFu ? first : raw;
+        b[q] = src(P * y1 + (int)(s & 15), P * y2 + (int)((s >> 4) & 15), P * y3 + (int)((s >> 8) & 15),
+                   P * y4 + (int)(s >> 12));
+        if (raw == 0xFFFFu) b[q] = 0;
     }
+    unsigned w[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < 16; ++q) w[q >> 2] |= b[q] << (8 * (q & 3));
+    return v4u{w[0], w[1], w[2], w[3]};
+}
+
+// Delta in the Cartier-split layout dl (global), built by 16-byte chunks:
+// chunk m of row y in region j holds Delta[p y + sigma] for the region's
+// columns 16m .. 16m+15 (sigma from the column table, zero for padding).
+// src(x1, x2, x3, x4) returns Delta at a position of degree D.  Two chunks per
+// thread and iteration keep 32 independent gathers in flight.
+template <int P, class Src>
+__device__ inline void cartier_split(Src &&src, uint8_t *dl)
+{
+    constexpr int64_t NCH = ThetaGeo<P>::BYTES / 16;
+    const int64_t nt = blockDim.x;
+    int64_t ch = threadIdx.x;
+    for (; ch + nt < NCH; ch += 2 * nt) {
+        const v4u a = cartier_chunk<P>(src, ch), b = cartier_chunk<P>(src, ch + nt);
+        gstore16(dl + ch * 16, a);
+        gstore16(dl + (ch + nt) * 16, b);
+    }
+    if (ch < NCH) gstore16(dl + ch * 16, cartier_chunk<P>(src, ch));
 }
 
 // theta(a) for the coarse parts of degree J0: row y of region J0 (Delta at

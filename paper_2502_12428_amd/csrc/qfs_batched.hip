@@ -213,6 +213,29 @@ __global__ __launch_bounds__(256) void k_plan(uint32_t *plan)
         int off = 0;
         for (int i = 0; i < tid; ++i) off += cnt[i];
         for (int b = b0; b < b1; ++b) off += plan_block_emit(m, b, keep, [&](int i, uint32_t t) { out[off + i] = t; });
+        __syncthreads();
+        // bounding box of every group of 16 entries
+        const int len = (int)(band ? kPT<P>.nlen[k] : kPT<P>.blen[k]);
+        uint32_t *gb = plan + (band ? kPT<P>.ngoff[k] : kPT<P>.gboff[k]);
+        for (int g = tid; g * 16 < len; g += 256) {
+            int m1 = 0, m2 = 0, m3 = 0, l1 = 1 << 15, l2 = 1 << 15, l3 = 1 << 15, wl = 1 << 15, wh = 0;
+            for (int i = g * 16; i < len && i < g * 16 + 16; ++i) {
+                const uint32_t t = out[i];
+                const int c1 = unp0(t), c2 = unp1(t), c3 = unp2(t), w = T1 * c1 + T2 * c2 + T3 * c3;
+                m1 = max(m1, c1);
+                m2 = max(m2, c2);
+                m3 = max(m3, c3);
+                l1 = min(l1, c1);
+                l2 = min(l2, c2);
+                l3 = min(l3, c3);
+                wl = min(wl, w);
+                wh = max(wh, w);
+            }
+            gb[4 * g] = (uint32_t)m1 | ((uint32_t)m2 << 16);
+            gb[4 * g + 1] = (uint32_t)m3 | ((uint32_t)l1 << 16);
+            gb[4 * g + 2] = (uint32_t)l2 | ((uint32_t)l3 << 16);
+            gb[4 * g + 3] = (uint32_t)wl | ((uint32_t)wh << 16);
+        }
         return;
     }
     // shell lists: one column slab c1 per thread, any order
@@ -411,7 +434,7 @@ __device__ __attribute__((always_inline)) inline unsigned epilogue(int c1, int c
 // W_{delta + Delta_s}), then issues 4 * NB products
 // D[s][tile] += W[s][(delta, s')] * A[(delta, s')][tile].
 template <int P, int NB>
-__device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *list, int nbase, int gfirst, int nk, int cap,
+__device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *list, const uint32_t *gbox, int nbase, int gfirst, int nk, int cap,
                          const uint8_t *W, const uint8_t *__restrict__ Ain, uint8_t *Aout, bool last,
                          const int *toff_l, const uint32_t *widx_l, const uint32_t *qbox_l, uint16_t *qlist,
                          const EpiCtx &ec)
@@ -422,8 +445,9 @@ __device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *l
 
     int64_t base[NB];
     bool ok[NB], gex[NB];
-    int gmax1[NB], gmax2[NB], gmax3[NB], gwmin[NB], gmin1[NB], gmin2[NB], gmin3[NB], gwmax[NB];
     uint32_t tpk[NB];
+    // the set's bounding box from the groups' boxes (uniform loads)
+    int smax1 = 0, smax2 = 0, smax3 = 0, swmin = 1 << 30, smin1 = 1 << 30, smin2 = 1 << 30, smin3 = 1 << 30, swmax = 0;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int g0 = (gfirst + b) * 16;
@@ -432,42 +456,41 @@ __device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *l
         ok[b] = idx < nbase;
         const uint32_t t = gex[b] ? list[ok[b] ? idx : g0] : 0u;
         tpk[b] = t;
-        const int c1 = unp0(t), c2 = unp1(t), c3 = unp2(t);
-        base[b] = box_tile<P>(c1, c2, c3);
-        gmax1[b] = uniform(wave_max(c1));
-        gmax2[b] = uniform(wave_max(c2));
-        gmax3[b] = uniform(wave_max(c3));
-        gwmin[b] = uniform(wave_min(T1 * c1 + T2 * c2 + T3 * c3));
-        gmin1[b] = uniform(wave_min(c1));
-        gmin2[b] = uniform(wave_min(c2));
-        gmin3[b] = uniform(wave_min(c3));
-        gwmax[b] = uniform(wave_max(T1 * c1 + T2 * c2 + T3 * c3));
+        base[b] = box_tile<P>(unp0(t), unp1(t), unp2(t));
+        if (gex[b]) {
+            const uint32_t *gb = gbox + 4 * (gfirst + b);
+            const uint32_t w0 = gb[0], w1 = gb[1], w2 = gb[2], w3 = gb[3];
+            smax1 = max(smax1, (int)(w0 & 0xFFFFu));
+            smax2 = max(smax2, (int)(w0 >> 16));
+            smax3 = max(smax3, (int)(w1 & 0xFFFFu));
+            smin1 = min(smin1, (int)(w1 >> 16));
+            smin2 = min(smin2, (int)(w2 & 0xFFFFu));
+            smin3 = min(smin3, (int)(w2 >> 16));
+            swmin = min(swmin, (int)(w3 & 0xFFFFu));
+            swmax = max(swmax, (int)(w3 >> 16));
+        }
     }
+    smax1 = uniform(smax1);
+    smax2 = uniform(smax2);
+    smax3 = uniform(smax3);
+    smin1 = uniform(smin1);
+    smin2 = uniform(smin2);
+    smin3 = uniform(smin3);
+    swmin = uniform(swmin);
+    swmax = uniform(swmax);
     v4i acc[4][NB];
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[s][b] = v4i{0, 0, 0, 0};
 
-    // Bounding box of the set's tiles.  A quad whose input tiles q - delta all lie
-    // outside A_k (a negative coordinate, or weight above deg A_k) contributes
-    // nothing and is skipped.  For the quads that are processed, every group and
-    // every shift is multiplied: tiles outside A_k read the zero halo or the
-    // zeroed shell and the zero W block adds nothing, so the products stay exact
-    // and the loop has no branches around the matrix instructions.
-    int smax1 = 0, smax2 = 0, smax3 = 0, swmin = 1 << 30, smin1 = 1 << 30, smin2 = 1 << 30, smin3 = 1 << 30, swmax = 0;
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-        if (gex[b]) {
-            smax1 = max(smax1, gmax1[b]);
-            smax2 = max(smax2, gmax2[b]);
-            smax3 = max(smax3, gmax3[b]);
-            swmin = min(swmin, gwmin[b]);
-            smin1 = min(smin1, gmin1[b]);
-            smin2 = min(smin2, gmin2[b]);
-            smin3 = min(smin3, gmin3[b]);
-            swmax = max(swmax, gwmax[b]);
-        }
+    // A quad whose input tiles q - delta all lie outside A_k (a negative
+    // coordinate, or weight above deg A_k; in the capped chain also outside
+    // the cap) contributes nothing and is skipped.  For the quads that are
+    // processed, every group and every shift is multiplied: tiles outside A_k
+    // read the zero halo or the zeroed shell and the zero W block adds
+    // nothing, so the products stay exact and the loop has no branches
+    // around the matrix instructions.
     // the quads this set needs, in order, into the wave's list in LDS
     int nq = 0;
     for (int q0 = 0; q0 < X::NQX; q0 += 64) {
@@ -641,6 +664,7 @@ __device__ __attribute__((always_inline)) inline void run_chain(bool band, const
         uint8_t *Aout = (k & 1) ? buf1 : buf0;
         const int nbase = (int)(band ? kPT<P>.nlen[k] : kPT<P>.blen[k]);
         const uint32_t *list = plan + (band ? kPT<P>.noff[k] : kPT<P>.boff[k]);
+        const uint32_t *gbox = plan + (band ? kPT<P>.ngoff[k] : kPT<P>.gboff[k]);
         const bool last = (k == P - 1);
         ec.win = band && last;
         // whole rounds of DEEP_NB-group sets, one per wave; the groups left
@@ -648,11 +672,11 @@ __device__ __attribute__((always_inline)) inline void run_chain(bool band, const
         const int ngroups = (nbase + 15) / 16;
         const int rounds = ngroups / (DEEP_NB * DEEP_NW);
         for (int i = 0; i < rounds; ++i)
-            mfma_set<P, DEEP_NB>(list, nbase, (i * DEEP_NW + wave) * DEEP_NB, k * d, cap, W, Ain, Aout, last, toff_l,
+            mfma_set<P, DEEP_NB>(list, gbox, nbase, (i * DEEP_NW + wave) * DEEP_NB, k * d, cap, W, Ain, Aout, last, toff_l,
                                  widx_l, qbox_l, qlist_w, ec);
         constexpr int NB2 = DEEP_NB / 2;
         for (int g = rounds * DEEP_NB * DEEP_NW + wave * NB2; g < ngroups; g += DEEP_NW * NB2)
-            mfma_set<P, NB2>(list, nbase, g, k * d, cap, W, Ain, Aout, last, toff_l, widx_l, qbox_l, qlist_w, ec);
+            mfma_set<P, NB2>(list, gbox, nbase, g, k * d, cap, W, Ain, Aout, last, toff_l, widx_l, qbox_l, qlist_w, ec);
         if (!last)
             zero_shell<P>(plan + (band ? kPT<P>.hoff[k] : kPT<P>.foff[k]), (int)(band ? kPT<P>.hlen[k] : kPT<P>.flen[k]),
                           Aout);

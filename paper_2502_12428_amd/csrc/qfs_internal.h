@@ -122,9 +122,12 @@ __host__ __device__ inline bool quad_needed(int m1, int m2, int m3, int wmin, in
 //  band list k (k = 1..P-1): the base tiles of list k that band_tile keeps;
 //  band shell list k (k = 1..P-2): the tiles of shell list k whose coordinates
 //    are all T_i c_i <= p^2 - 1, the only ones the capped chain reads.
+// The base and band lists come with the bounding box of every group of 16
+// entries (4 words at gboff / ngoff: max c1 | max c2 << 16, max c3 | min c1
+// << 16, min c2 | min c3 << 16, min w | max w << 16).
 template <int P>
 struct PlanTable {
-    int64_t blen[P], boff[P], flen[P], foff[P], nlen[P], noff[P], hlen[P], hoff[P];
+    int64_t blen[P], boff[P], flen[P], foff[P], nlen[P], noff[P], hlen[P], hoff[P], gboff[P], ngoff[P];
     int64_t words;
 };
 // The c3 range [lo, hi] (empty if lo > hi) of shell list k (cap = CAP_NONE)
@@ -225,6 +228,12 @@ constexpr PlanTable<P> make_plan_table()
         t.hoff[k] = o;
         t.hlen[k] = k >= 1 && k <= P - 2 ? shell_tiles<P>(k, P * P - 1) : 0;
         o += t.hlen[k];
+    }
+    for (int k = 0; k < P; ++k) {
+        t.gboff[k] = o;
+        o += 4 * ((t.blen[k] + 15) / 16);
+        t.ngoff[k] = o;
+        o += 4 * ((t.nlen[k] + 15) / 16);
     }
     t.words = o;
     return t;

@@ -35,11 +35,11 @@ INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix peak, 5.0 POP/s
 TRAFFIC_SOURCES = ("qfs_batched.hip", "qfs_device.h", "qfs_common.h", "qfs_internal.h")
 TRAFFIC = {
     "workload": "p7_batch65536",
-    "sources_sha256": "38d4f92e7ba1e2957d5564ef46c57719a1c6abdd524ce2f7b31b4082197fd45f",
-    "fetch_scale": 524288.0 / 262169.75, "write_scale": 1.0,
+    "sources_sha256": "45d48324c9c304e3bbdc1feb3eff5c7208f4af44018827ba58652ef426ceece8",
+    "fetch_scale": 524288.0 / 262170.3125, "write_scale": 1.0,
     "kernels": {  # kernel name -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
-        "k_deep<7, true>": (43950545.0, 11113041.59375),
-        "k_deep<7, false>": (38268027.125, 10467525.90625),
+        "k_deep<7, true>": (37163116.65, 11105807.90),
+        "k_deep<7, false>": (40775594.36, 8770118.91),
     },
     "profile": "profiles/k_deep7_p7_batch65536_counters.md",
 }

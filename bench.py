@@ -35,11 +35,11 @@ INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix peak, 5.0 POP/s
 TRAFFIC_SOURCES = ("qfs_batched.hip", "qfs_device.h", "qfs_common.h", "qfs_internal.h")
 TRAFFIC = {
     "workload": "p7_batch65536",
-    "sources_sha256": "45d48324c9c304e3bbdc1feb3eff5c7208f4af44018827ba58652ef426ceece8",
-    "fetch_scale": 524288.0 / 262170.3125, "write_scale": 1.0,
+    "sources_sha256": "12267f0b329faaf834c703cd1171738c50e7e006e300c6f62a48fe67e2e5ab86",
+    "fetch_scale": 524288.0 / 262169.3125, "write_scale": 1.0,
     "kernels": {  # kernel name -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
-        "k_deep<7, true>": (37163116.65, 11105807.90),
-        "k_deep<7, false>": (40775594.36, 8770118.91),
+        "k_deep<7, true>": (26491290.80, 17965394.18),
+        "k_deep<7, false>": (31110177.70, 13173275.15),
     },
     "profile": "profiles/k_deep7_p7_batch65536_counters.md",
 }
@@ -72,27 +72,32 @@ def count_terms_below(X, d):
     return tot
 
 
-def band_macs(p):
-    """Multiply-adds the capped chain needs: for k = 1..p-1 the products g~[t] A_k[x-t] over the
-    outputs x of A_(k+1) with all four exponents <= p^2-1 (last step: the window p^2-1-d..p^2-1)."""
+def band_macs(p, J=None):
+    """Multiply-adds the capped chain needs with the multiplier m = f~^J mod p^2 (degree dm = 4J,
+    NF = p(p-1)/J factors; J = p-1 is the chain of g~): for k = 1..NF-1 the products m[t] A_k[x-t]
+    over the outputs x of A_(k+1) with all four exponents <= p^2-1 (last step: the window
+    p^2-1-d..p^2-1 that the first theta test reads, d = 4(p-1))."""
     import numpy as np
-    d, E = 4 * (p - 1), p * p - 1
+    J = p - 1 if J is None else J
+    d, dm, nf, E = 4 * (p - 1), 4 * J, p * (p - 1) // J, p * p - 1
     tot = 0
-    for k in range(1, p):
-        n = (k + 1) * d
-        lo = E - d if k == p - 1 else 0
+    for k in range(1, nf):
+        n = (k + 1) * dm
+        lo = E - d if k == nf - 1 else 0
         r = np.arange(lo, E + 1, dtype=np.int64)
         x1, x2, x3 = (a.ravel() for a in np.meshgrid(r, r, r, indexing="ij"))
         x4 = n - x1 - x2 - x3
         m = (x4 >= lo) & (x4 <= E)
-        tot += int(count_terms_below(np.stack([x1[m], x2[m], x3[m], x4[m]], 1), d).sum())
+        tot += int(count_terms_below(np.stack([x1[m], x2[m], x3[m], x4[m]], 1), dm).sum())
     return tot
 
 
-def delta1_macs(p):
-    """Useful multiply-adds of the chain g~^(k+1) = g~^k * g~, k = 1..p-1 (dense schoolbook counts)."""
-    d = 4 * (p - 1)
-    return sum(comb(d * k + 3, 3) * comb(d + 3, 3) for k in range(1, p))
+def delta1_macs(p, J=None):
+    """Useful multiply-adds of the chain A_(k+1) = A_k * m, k = 1..NF-1, m = f~^J mod p^2 of degree
+    dm = 4J (dense schoolbook counts; J = p-1 is the chain of g~)."""
+    J = p - 1 if J is None else J
+    dm, nf = 4 * J, p * (p - 1) // J
+    return sum(comb(dm * k + 3, 3) * comb(dm + 3, 3) for k in range(1, nf))
 
 
 def theta_macs(p, h, skip_first, bound=10):
@@ -216,25 +221,33 @@ def main():
     per_call = {k: v / max(calls, 1) for k, v in stage_ms.items()}
     band_on = qfs.get_option("height_band") == 1
     is_deep = (heights == 0) | (heights >= 2)
+    # useful work per launch: the dense products of the chain of g~ (the
+    # algorithm's formulation, Algorithm 1: g~^k * g~, k = 1..p-1; capped in the
+    # band kernel) plus theta; "chain_ops" counts the products of the chain the
+    # kernels actually run (multiplier m = f~^J mod p^2, same result, fewer MACs)
     kernels = {}
     for q in (3, 5, 7, 11):
         hq = heights[is_deep & (P == q)]
         beyond = hq[(hq == 0) | (hq >= 3)] if band_on else hq
         lg = comb(4 * q - 1, 3)
+        J = qfs.get_option("chain_power_p%d" % q)
         if band_on and hq.size:
             kernels["k_deep<%d, true>" % q] = {
-                "ms": per_call["band_p%d" % q], "surfaces": int(hq.size),
+                "ms": per_call["band_p%d" % q], "surfaces": int(hq.size), "chain_power": J,
                 "useful_ops": 2.0 * hq.size * (band_macs(q) + lg),
+                "chain_ops": 2.0 * hq.size * (band_macs(q, J) + lg),
                 "mfma": int(hq.size) * qfs.mfma_per_surface(q, band=True)}
         if beyond.size:
+            th = sum(theta_macs(q, int(x), band_on) for x in beyond)
             kernels["k_deep<%d, false>" % q] = {
-                "ms": per_call["deep_p%d" % q], "surfaces": int(beyond.size),
-                "useful_ops": 2.0 * (beyond.size * delta1_macs(q) +
-                                     sum(theta_macs(q, int(x), band_on) for x in beyond)),
+                "ms": per_call["deep_p%d" % q], "surfaces": int(beyond.size), "chain_power": J,
+                "useful_ops": 2.0 * (beyond.size * delta1_macs(q) + th),
+                "chain_ops": 2.0 * (beyond.size * delta1_macs(q, J) + th),
                 "mfma": int(beyond.size) * qfs.mfma_per_surface(q)}
     for name, kd in kernels.items():
         sec = kd["ms"] * 1e-3
         kd["achieved_tops"] = kd["useful_ops"] / sec / 1e12 if sec > 0 else 0.0
+        kd["chain_useful_tops"] = kd["chain_ops"] / sec / 1e12 if sec > 0 else 0.0
         kd["executed_mfma_tops"] = kd["mfma"] * 32768.0 / sec / 1e12 if sec > 0 else 0.0
         kd["executed_mfma_frac"] = kd["executed_mfma_tops"] / INT8_PEAK_TOPS
         kd["traffic"] = measured_traffic(args.workload, name)
@@ -287,6 +300,8 @@ def main():
             "traffic_profile": TRAFFIC["profile"] if traffic else None,
             "kernel_ms_per_launch": kd["ms"],
             "useful_ops_per_launch": kd["useful_ops"],
+            "chain_power": kd["chain_power"],
+            "chain_useful_tops": kd["chain_useful_tops"],
             "surfaces_per_launch": kd["surfaces"],
             "executed_mfma_tops": kd["executed_mfma_tops"],
             "executed_mfma_frac": kd["executed_mfma_frac"],

@@ -196,6 +196,11 @@ int64_t qfs_mfma_per_surface(int p, int pass);
  *   "height_graph" (default 1): replay cached hipGraphs of the qfs_height
  *     launch sequence (see qfs_height); 0 launches the kernels directly.
  *   "height_graphs_cached" (read only): number of graphs in the cache.
+ *   "chain_power_p3", "chain_power_p5", "chain_power_p7", "chain_power_p11"
+ *     (read only): the power J of the deep chain's multiplier m = f~^J mod p^2
+ *     at that prime.  g~^p mod p^2 (Algorithm 1) is formed as
+ *     m^(p(p-1)/J) = f~^(p(p-1)), which equals g~^p mod p^2 since
+ *     g~ = f~^(p-1) mod p; J = p-1 multiplies by g~ itself.
  *   "deep_slots" (default 0 = one per compute unit): persistent workgroups
  *     of the deep kernels, each with its own slot of workspace; it changes
  *     the *_workspace_bytes results, so query them after setting it.

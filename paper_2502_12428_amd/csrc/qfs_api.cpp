@@ -254,6 +254,7 @@ int qfs_delta1(int p, int batch, const uint8_t *f, uint8_t *g_out, uint8_t *delt
     da.counters = counters;
     da.queue = (const int32_t *)(w + L.queue[pi]);
     da.gq = w + L.gq[pi];
+    da.f = f;
     da.plan = (const uint32_t *)(w + L.plan[pi]);
     da.slots = w + L.slots;
     da.slot_bytes = L.slot_stride[pi];
@@ -348,6 +349,7 @@ static int enqueue_height(int batch, const int32_t *p, const uint8_t *f, int bou
         da.queue = (const int32_t *)(w + L.queue[i]);
         da.queue2 = (int32_t *)(w + L.queue2[i]);
         da.gq = w + L.gq[i];
+        da.f = f;
         da.plan = (const uint32_t *)(w + L.plan[i]);
         da.slots = w + L.slots;
         da.slot_bytes = L.slot_stride[i];
@@ -517,6 +519,10 @@ int64_t qfs_get_option(const char *name)
         std::lock_guard<std::mutex> lk(g_graphs.m);
         return (int64_t)g_graphs.v.size();
     }
+    if (name && std::strcmp(name, "chain_power_p3") == 0) return Geo<3>::J;
+    if (name && std::strcmp(name, "chain_power_p5") == 0) return Geo<5>::J;
+    if (name && std::strcmp(name, "chain_power_p7") == 0) return Geo<7>::J;
+    if (name && std::strcmp(name, "chain_power_p11") == 0) return Geo<11>::J;
     return fail(QFS_EINVAL, "qfs_get_option: unknown option");
 }
 

@@ -6,10 +6,11 @@
 //   fail it ("deep" surfaces) are compacted into a per-prime queue together
 //   with g.
 // Deep kernel (persistent; each workgroup pops surfaces from the queue):
-//   g~^p mod p^2 by the chain A_{k+1} = A_k * g~ (k = 1..p-1) on int8 matrix
-//   cores with int32 accumulation (Algorithm 1, line 2), the Delta_1 epilogue
-//   fused into the last product (Algorithm 1, lines 3-5), then the theta loop
-//   of Algorithm 3 with its one-coefficient test.
+//   g~^p mod p^2 (Algorithm 1) as m^NF for the multiplier m = f~^J mod p^2,
+//   by the chain A_{k+1} = A_k * m (k = 1..NF-1) on int8 matrix cores with
+//   int32 accumulation, the Delta_1 epilogue fused into the last product
+//   (Algorithm 1), then the theta loop of Algorithm 3 with its
+//   one-coefficient test.
 #include <algorithm>
 #include <cstdlib>
 #include <vector>
@@ -190,10 +191,10 @@ template <int P>
 __global__ __launch_bounds__(256) void k_plan(uint32_t *plan)
 {
     using X = GeoX<P>;
-    constexpr int d = 4 * (P - 1);
-    const int kind = blockIdx.x / P, k = blockIdx.x % P;  // 0 base, 1 shell, 2 band, 3 band shell
-    if (kind == 1 ? (k > P - 2) : kind == 3 ? (k < 1 || k > P - 2) : (k < 1)) return;
-    const int m = (k + 1) * d;
+    constexpr int dm = X::dm, NF = X::NF;
+    const int kind = blockIdx.x / NF, k = blockIdx.x % NF;  // 0 base, 1 shell, 2 band, 3 band shell
+    if (kind == 1 ? (k > NF - 2) : kind == 3 ? (k < 1 || k > NF - 2) : (k < 1)) return;
+    const int m = (k + 1) * dm;
     uint32_t *out = plan + (kind == 0 ? kPT<P>.boff[k] : kind == 1 ? kPT<P>.foff[k] : kind == 2 ? kPT<P>.noff[k]
                                                                                           : kPT<P>.hoff[k]);
     __shared__ int cnt[256];
@@ -265,10 +266,10 @@ __global__ __launch_bounds__(256) void k_plan(uint32_t *plan)
 hipError_t launch_plan(int p, uint32_t *plan, hipStream_t s)
 {
     switch (p) {
-    case 3: hipLaunchKernelGGL(k_plan<3>, dim3(4 * 3), dim3(256), 0, s, plan); break;
-    case 5: hipLaunchKernelGGL(k_plan<5>, dim3(4 * 5), dim3(256), 0, s, plan); break;
-    case 7: hipLaunchKernelGGL(k_plan<7>, dim3(4 * 7), dim3(256), 0, s, plan); break;
-    case 11: hipLaunchKernelGGL(k_plan<11>, dim3(4 * 11), dim3(256), 0, s, plan); break;
+    case 3: hipLaunchKernelGGL(k_plan<3>, dim3(4 * Geo<3>::NF), dim3(256), 0, s, plan); break;
+    case 5: hipLaunchKernelGGL(k_plan<5>, dim3(4 * Geo<5>::NF), dim3(256), 0, s, plan); break;
+    case 7: hipLaunchKernelGGL(k_plan<7>, dim3(4 * Geo<7>::NF), dim3(256), 0, s, plan); break;
+    case 11: hipLaunchKernelGGL(k_plan<11>, dim3(4 * Geo<11>::NF), dim3(256), 0, s, plan); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -297,9 +298,15 @@ struct DeepLds {
     static constexpr int LGA = (LG + 15) / 16 * 16;
     static constexpr int APA = (ThetaGeo<P>::APERM + 15) / 16 * 16;
     static constexpr int WB = w_in_lds<P>() ? (int)((X::W_BYTES + 15) / 16 * 16) : 0;
+    // the multiplier m = f~^J mod p^2 (J < p-1; for J = p-1, m = g~ is g itself)
+    static constexpr bool OWN_M = Geo<P>::J < P - 1;
+    static constexpr int LMA = OWN_M ? (int)((num_mono(X::dm) + 15) / 16 * 16) : 0;
     static constexpr int off_w = 0;
     static constexpr int off_g = off_w + WB;
-    static constexpr int off_aperm = off_g + LGA;
+    static constexpr int off_m0 = off_g + LGA;
+    static constexpr int off_m1 = off_m0 + LMA;
+    static constexpr int off_taps = off_m1 + LMA;
+    static constexpr int off_aperm = off_taps + (OWN_M ? 48 * 4 : 0);
     static constexpr int off_toff = off_aperm + APA;
     static constexpr int off_widx = off_toff + 4 * (X::NVXP + 4);
     static constexpr int off_qbox = off_widx + 8 * (X::NVXP + 4);
@@ -317,13 +324,13 @@ __device__ inline int64_t box_tile(int c1, int c2, int c3)
     return ((int64_t)(c1 + X::H1) * X::B2 + (c2 + X::H2)) * X::B3 + (c3 + X::H3);
 }
 
-// W[v][s][s'] = g~[T*v + s - s'] for v in V (dehomogenised, zero outside the
-// simplex of degree d); block NV is all zero.
+// W[v][s][s'] = m[T*v + s - s'] for v in V (dehomogenised, zero outside the
+// simplex of degree dm); block NV is all zero.
 template <int P>
 __device__ void build_w(const uint8_t *g, uint8_t *W)
 {
     using X = GeoX<P>;
-    constexpr int d = X::d;
+    constexpr int d = X::dm;
     for (int row = threadIdx.x; row < (X::NV + 1) * 16; row += blockDim.x) {
         const int v = row >> 4, s = row & 15;
         const int s1 = s >> 3, s2 = (s >> 2) & 1, s3 = s & 3;
@@ -348,11 +355,11 @@ __device__ void build_w(const uint8_t *g, uint8_t *W)
     }
 }
 
-// A_1 = g~ on the shell list 0 (every tile with w(c) <= 2d + 4; zero beyond degree d).
+// A_1 = m on the shell list 0 (every tile with w(c) <= 2 dm + 4; zero beyond degree dm).
 template <int P>
 __device__ void init_a1(const uint8_t *g, const uint32_t *list, int ntiles, uint8_t *A)
 {
-    constexpr int d = 4 * (P - 1);
+    constexpr int d = GeoX<P>::dm;
     for (int i = threadIdx.x; i < ntiles; i += blockDim.x) {
         const uint32_t t = list[i];
         const int c1 = unp0(t), c2 = unp1(t), c3 = unp2(t);
@@ -645,27 +652,28 @@ struct BoxDelta {
     }
 };
 
-// The chain A_{k+1} = A_k * g~, k = 1..P-1, into the two tile boxes, from the
-// W blocks and g already in place: in full, or (band) only the super-tiles
+// The chain A_{k+1} = A_k * m, k = 1..NF-1, into the two tile boxes, from the
+// W blocks and m already in place: in full, or (band) only the super-tiles
 // that the height-2 test depends on, ending in the window of Delta it reads.
+// A_NF ends in buf[(NF-1) & 1].
 template <int P>
-__device__ __attribute__((always_inline)) inline void run_chain(bool band, const uint32_t *plan, const uint8_t *g_l,
+__device__ __attribute__((always_inline)) inline void run_chain(bool band, const uint32_t *plan, const uint8_t *m_l,
                                                                const uint8_t *W, uint8_t *buf0, uint8_t *buf1,
                                                                const int *toff_l, const uint32_t *widx_l,
                                                                const uint32_t *qbox_l, uint16_t *qlist_w, EpiCtx ec)
 {
-    constexpr int d = 4 * (P - 1);
+    constexpr int d = GeoX<P>::dm, NF = GeoX<P>::NF;
     const int wave = uniform(threadIdx.x >> 6);
     const int cap = band ? P * P - 1 : CAP_NONE;
-    init_a1<P>(g_l, plan + kPT<P>.foff[0], (int)kPT<P>.flen[0], buf0);
+    init_a1<P>(m_l, plan + kPT<P>.foff[0], (int)kPT<P>.flen[0], buf0);
     __syncthreads();
-    for (int k = 1; k < P; ++k) {
+    for (int k = 1; k < NF; ++k) {
         const uint8_t *Ain = (k & 1) ? buf0 : buf1;
         uint8_t *Aout = (k & 1) ? buf1 : buf0;
         const int nbase = (int)(band ? kPT<P>.nlen[k] : kPT<P>.blen[k]);
         const uint32_t *list = plan + (band ? kPT<P>.noff[k] : kPT<P>.boff[k]);
         const uint32_t *gbox = plan + (band ? kPT<P>.ngoff[k] : kPT<P>.gboff[k]);
-        const bool last = (k == P - 1);
+        const bool last = (k == NF - 1);
         ec.win = band && last;
         // whole rounds of DEEP_NB-group sets, one per wave; the groups left
         // over go out in sets of DEEP_NB/2 so that more waves share the tail
@@ -760,8 +768,17 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
         const int qpos = q2 ? a.queue2[pos] : pos;  // position in the first queue
         const int surf = a.queue[qpos];
         for (int i = tid; i < LG; i += DEEP_NT) g_l[i] = a.gq[(size_t)qpos * LG + i];
+        const uint8_t *m_l = g_l;
+        if constexpr (L::OWN_M) {
+            __shared__ __align__(16) uint8_t f35[48];
+            __shared__ int ntap;
+            if (tid < 35) f35[tid] = (uint8_t)(a.f[(size_t)surf * 35 + tid] % P);
+            __syncthreads();
+            m_l = fpow_mod_lds<Geo<P>::J, P * P>(f35, lds + L::off_m0, lds + L::off_m1, (uint32_t *)(lds + L::off_taps),
+                                                 &ntap);
+        }
         __syncthreads();
-        build_w<P>(g_l, W);
+        build_w<P>(m_l, W);
         __syncthreads();
 
         EpiCtx ec;
@@ -771,7 +788,7 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
         ec.g = g_l;
         ec.err = &s_err;
         uint16_t *qlist_w = qlist_l + wave * L::QSTRIDE;
-        run_chain<P>(BAND, a.plan, g_l, W, buf[0], buf[1], toff_l, widx_l, qbox_l, qlist_w, ec);
+        run_chain<P>(BAND, a.plan, m_l, W, buf[0], buf[1], toff_l, widx_l, qbox_l, qlist_w, ec);
         const bool err = s_err != 0;
 
         if (BAND) {
@@ -779,7 +796,7 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
             int hv = -1;
             if (err)
                 hv = -5; /* QFS_EARITH */
-            else if (theta_test_box<P>(buf[(P - 1) & 1], g_l, red) != 0)
+            else if (theta_test_box<P>(buf[(X::NF - 1) & 1], g_l, red) != 0)
                 hv = 2;
             else if (a.bound == 2)
                 hv = 0;
@@ -802,7 +819,7 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
         // Algorithm 3's loop: the test reads c(theta(a)) only; theta(a) in full
         // is needed only when the surface goes on to the next h.  Surfaces from
         // the second queue are known to fail the first test.
-        const uint8_t *dbox = buf[(P - 1) & 1];
+        const uint8_t *dbox = buf[(X::NF - 1) & 1];
         int h = 0;
         bool split = false;
         for (int hh = 2; hh <= a.bound; ++hh) {
@@ -884,10 +901,10 @@ template <int P>
 static int64_t mfma_count_p(bool band)
 {
     using X = GeoX<P>;
-    constexpr int d = X::d, E = P * P - 1;
+    constexpr int d = X::dm, E = P * P - 1;
     static const DeltaTableX<P> DX = make_delta_table_x<P>();
     int64_t total = 0;
-    for (int k = 1; k < P; ++k) {
+    for (int k = 1; k < X::NF; ++k) {
         const int n = (k + 1) * d, nk = k * d, cap = band ? E : (1 << 20);
         std::vector<uint32_t> tiles;  // the list in k_plan's order
         const PlanBlocks nb = plan_blocks(n);

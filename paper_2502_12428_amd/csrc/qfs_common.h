@@ -129,32 +129,63 @@ constexpr CapTable<P> make_cap_table()
 }
 
 // ---------------------------------------------------------------------------
-// Block-Toeplitz geometry for the matrix-core product C = A * g (g of degree d).
+// The deep chain.  Delta_1 needs g~^p mod p^2 (Algorithm 1).  Since
+// g~ = f~^(p-1) + p h for some integral h, (g~ + p h)^p = g~^p mod p^2, so
+// g~^p = f~^(p(p-1)) = m^NF mod p^2 for the multiplier m = f~^J mod p^2 with
+// any J dividing p(p-1), NF = p(p-1)/J.  The chain A_1 = m,
+// A_{k+1} = A_k * m (k = 1..NF-1) trades fewer, larger products (J = p-1,
+// where m = g~ is used directly) against more, smaller ones (J = 1, m = f~).
+// The values of J per prime are chosen by measurement.
+// ---------------------------------------------------------------------------
+#ifndef QFS_CHAIN_J3
+#define QFS_CHAIN_J3 2
+#endif
+#ifndef QFS_CHAIN_J5
+#define QFS_CHAIN_J5 2
+#endif
+#ifndef QFS_CHAIN_J7
+#define QFS_CHAIN_J7 3
+#endif
+#ifndef QFS_CHAIN_J11
+#define QFS_CHAIN_J11 2
+#endif
+template <int P>
+constexpr int chain_j()
+{
+    return P == 3 ? QFS_CHAIN_J3 : P == 5 ? QFS_CHAIN_J5 : P == 7 ? QFS_CHAIN_J7 : QFS_CHAIN_J11;
+}
+
+// ---------------------------------------------------------------------------
+// Block-Toeplitz geometry for the matrix-core product C = A * m (m of degree
+// dm = 4J).
 //
 // Dehomogenised positions are cut into tiles of T = (2,2,4) positions (16
 // bytes, position s = s1*8 + s2*4 + s3 inside the tile).  With output tile q
 // and input tile q - delta, the product restricted to one pair of tiles is a
-// 16x16 matrix W_delta[s][s'] = g[T*delta + s - s'] applied to the 16 input
+// 16x16 matrix W_delta[s][s'] = m[T*delta + s - s'] applied to the 16 input
 // bytes.  V is the set of offsets delta whose block can be nonzero for a
-// form of degree d: some T*delta + s - s' lies in {x >= 0, x1+x2+x3 <= d}.
+// form of degree dm: some T*delta + s - s' lies in {x >= 0, x1+x2+x3 <= dm}.
 // ---------------------------------------------------------------------------
 constexpr int T1 = 2, T2 = 2, T3 = 4, TILE = 16;
 
 template <int P>
 struct Geo {
-    static constexpr int d = 4 * (P - 1);
-    static constexpr int D = P * d;
+    static constexpr int J = chain_j<P>();
+    static_assert(J >= 1 && J <= P - 1 && (P * (P - 1)) % J == 0, "J must divide p(p-1)");
+    static constexpr int dm = 4 * J;                // degree of the multiplier m
+    static constexpr int NF = P * (P - 1) / J;      // factors of the chain
+    static constexpr int D = 4 * P * (P - 1);       // degree of g~^p
     static constexpr bool valid(int a, int b, int c)
     {
         int s = 0;
         if (a >= 1) s += T1 * (a - 1) + 1;
         if (b >= 1) s += T2 * (b - 1) + 1;
         if (c >= 1) s += T3 * (c - 1) + 1;
-        return s <= d;
+        return s <= dm;
     }
-    static constexpr int H1 = (d - 1) / T1 + 1;   // largest delta coordinates
-    static constexpr int H2 = (d - 1) / T2 + 1;
-    static constexpr int H3 = (d - 1) / T3 + 1;
+    static constexpr int H1 = (dm - 1) / T1 + 1;   // largest delta coordinates
+    static constexpr int H2 = (dm - 1) / T2 + 1;
+    static constexpr int H3 = (dm - 1) / T3 + 1;
     static constexpr int count()
     {
         int n = 0;
@@ -195,7 +226,7 @@ __host__ __device__ constexpr int unp2(uint32_t v) { return (int)((v >> 20) & 10
 template <int P>
 struct GeoX {
     using G = Geo<P>;
-    static constexpr int d = G::d, D = G::D, NV = G::NV;
+    static constexpr int dm = G::dm, D = G::D, NV = G::NV, NF = G::NF;
     static constexpr int H1 = G::H1, H2 = G::H2, H3 = G::H3;
     static constexpr bool inV(int a, int b, int c)
     {

@@ -88,12 +88,12 @@ __device__ inline int compact_taps(const uint8_t *f35, uint32_t *taps)
     return __popcll(bal);
 }
 
-// g = f^(P-1) mod P in CNS order, computed in LDS by repeated multiplication
-// with the nonzero terms of f.  b0 and b1 must each hold C(4P-1,3) bytes,
-// taps 35 words.  Returns the buffer holding the result.  Must be called by
-// every thread of the block.
-template <int P>
-__device__ uint8_t *fpow_lds(const uint8_t *f35, uint8_t *b0, uint8_t *b1, uint32_t *taps, int *ntap)
+// f^J mod MOD in CNS order, computed in LDS by repeated multiplication with
+// the nonzero terms of f (coefficients in [0, MOD)).  b0 and b1 must each hold
+// C(4J+3,3) bytes, taps 35 words.  Returns the buffer holding the result.
+// Must be called by every thread of the block.
+template <int J, int MOD>
+__device__ uint8_t *fpow_mod_lds(const uint8_t *f35, uint8_t *b0, uint8_t *b1, uint32_t *taps, int *ntap)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int i = tid; i < 35; i += nt) b0[i] = f35[i];
@@ -104,7 +104,7 @@ __device__ uint8_t *fpow_lds(const uint8_t *f35, uint8_t *b0, uint8_t *b1, uint3
     __syncthreads();
     const int ntaps = *ntap;
     uint8_t *cur = b0, *nxt = b1;
-    for (int j = 1; j < P - 1; ++j) {
+    for (int j = 1; j < J; ++j) {
         const int n = 4 * (j + 1);
         const int len = (int)num_mono(n);
         for (int r = tid; r < len; r += nt) {
@@ -117,7 +117,7 @@ __device__ uint8_t *fpow_lds(const uint8_t *f35, uint8_t *b0, uint8_t *b1, uint3
                 if (e1 >= t1 && e2 >= t2 && e3 >= t3 && e4 >= t4)
                     acc += (int)(te >> 24) * cur[cns_rank(e2 - t2, e3 - t3, e4 - t4)];
             }
-            nxt[r] = (uint8_t)(acc % P);
+            nxt[r] = (uint8_t)(acc % MOD);
         }
         __syncthreads();
         uint8_t *tmp = cur;
@@ -125,6 +125,13 @@ __device__ uint8_t *fpow_lds(const uint8_t *f35, uint8_t *b0, uint8_t *b1, uint3
         nxt = tmp;
     }
     return cur;
+}
+
+// g = f^(P-1) mod P
+template <int P>
+__device__ uint8_t *fpow_lds(const uint8_t *f35, uint8_t *b0, uint8_t *b1, uint32_t *taps, int *ntap)
+{
+    return fpow_mod_lds<P - 1, P>(f35, b0, b1, taps, ntap);
 }
 
 __device__ inline unsigned dot16(const v4u a, const v4u b, unsigned acc)

@@ -68,9 +68,9 @@ __host__ __device__ inline int plan_block_emit(int m, int b, K &&keep, F &&emit)
 
 // The height-2 test reads c(theta(g)) = sum_c g[c] Delta[(p+1)e - c] only
 // (Section 3.4), i.e. Delta at the positions x with p^2-1-d <= x_i <= p^2-1
-// for all four coordinates.  Since A_{k+1}[x] = sum_t g~[t] A_k[x - t] with
-// t >= 0, those coefficients depend only on the coefficients of A_k whose
-// four coordinates are all <= p^2-1.  The capped chain computes just the
+// for all four coordinates (d = 4(p-1), the degree of g).  Since
+// A_{k+1}[x] = sum_t m[t] A_k[x - t] with t >= 0, those coefficients depend
+// only on the coefficients of A_k whose four coordinates are all <= p^2-1.  The capped chain computes just the
 // super-tiles that meet that region: band_tile tells whether the super-tile of
 // base tile (c1, c2, c3) at output degree n does (for n = D, the window).
 template <int P>
@@ -112,22 +112,24 @@ __host__ __device__ inline bool quad_needed(int m1, int m2, int m3, int wmin, in
            T3 * (l3 - (int)unp2(qmax)) <= cap && wmax - qwmin + (T1 - 1) + (T2 - 1) + (T3 - 1) >= nk - cap;
 }
 
-// Output-tile lists of the deep kernel (packed with pack3):
-//  base list k (k = 1..P-1): base tiles of the 2x2 super-tiles of output
-//    degree n = (k+1) d: c1, c2 even, w(c) = 2 c1 + 2 c2 + 4 c3 <= n;
-//  shell list 0: all tiles c >= 0 of the box with w(c) <= 2d + 4 (A_1 = g~
+// Output-tile lists of the deep kernel (packed with pack3), dm the degree of
+// the multiplier and NF the number of factors of the chain:
+//  base list k (k = 1..NF-1): base tiles of the 2x2 super-tiles of output
+//    degree n = (k+1) dm: c1, c2 even, w(c) = 2 c1 + 2 c2 + 4 c3 <= n;
+//  shell list 0: all tiles c >= 0 of the box with w(c) <= 2 dm + 4 (A_1 = m
 //    and the zeros the first product reads beyond its degree);
-//  shell list k (k = 1..P-2): the tiles with (k+1) d < w(c) <= (k+2) d + 4,
+//  shell list k (k = 1..NF-2): the tiles with (k+1) dm < w(c) <= (k+2) dm + 4,
 //    zeroed after step k because step k+1 reads them;
-//  band list k (k = 1..P-1): the base tiles of list k that band_tile keeps;
-//  band shell list k (k = 1..P-2): the tiles of shell list k whose coordinates
-//    are all T_i c_i <= p^2 - 1, the only ones the capped chain reads.
+//  band list k (k = 1..NF-1): the base tiles of list k that band_tile keeps;
+//  band shell list k (k = 1..NF-2): the tiles of shell list k whose
+//    coordinates are all T_i c_i <= p^2 - 1, the only ones the capped chain reads.
 // The base and band lists come with the bounding box of every group of 16
 // entries (4 words at gboff / ngoff: max c1 | max c2 << 16, max c3 | min c1
 // << 16, min c2 | min c3 << 16, min w | max w << 16).
 template <int P>
 struct PlanTable {
-    int64_t blen[P], boff[P], flen[P], foff[P], nlen[P], noff[P], hlen[P], hoff[P], gboff[P], ngoff[P];
+    static constexpr int NF = Geo<P>::NF;
+    int64_t blen[NF], boff[NF], flen[NF], foff[NF], nlen[NF], noff[NF], hlen[NF], hoff[NF], gboff[NF], ngoff[NF];
     int64_t words;
 };
 // The c3 range [lo, hi] (empty if lo > hi) of shell list k (cap = CAP_NONE)
@@ -136,8 +138,8 @@ template <int P>
 __host__ __device__ constexpr void shell_c3_range(int k, int cap, int c1, int c2, int &lo, int &hi)
 {
     using X = GeoX<P>;
-    constexpr int d = 4 * (P - 1);
-    const int n = k == 0 ? -1 : (k + 1) * d, m = (k + 2) * d + 4;
+    constexpr int dm = X::dm;
+    const int n = k == 0 ? -1 : (k + 1) * dm, m = (k + 2) * dm + 4;
     const int r = T1 * c1 + T2 * c2;
     lo = r > n ? 0 : (n - r) / T3 + 1;
     hi = m < r ? -1 : (m - r) / T3;
@@ -149,31 +151,31 @@ template <int P>
 __host__ __device__ constexpr int shell_cmax(int k, int cap)
 {
     using X = GeoX<P>;
-    const int m = (k + 2) * (4 * (P - 1)) + 4;
+    const int m = (k + 2) * GeoX<P>::dm + 4;
     int c = m / T1;
     if (c > X::C1) c = X::C1;
     if (c > cap / T1) c = cap / T1;
     return c;
 }
-template <int P>
+// Base tiles of degree n: base units u >= 0 with u1 + u2 + u3 <= n / 4.
 constexpr int64_t base_tiles(int n)
 {
-    int64_t cnt = 0;
-    for (int a = 0; T1 * a <= n; a += 2)
-        for (int b = 0; T1 * a + T2 * b <= n; b += 2) cnt += (n - T1 * a - T2 * b) / T3 + 1;
-    return cnt;
+    const int64_t u = n / 4;
+    return (u + 1) * (u + 2) * (u + 3) / 6;
 }
+// Tiles of shell list k: the c3 range depends on c1 + c2 only, so the columns
+// are counted per diagonal c1 + c2 = s (s + 1 of them for s <= cm, 2 cm - s + 1 beyond).
 template <int P>
 constexpr int64_t shell_tiles(int k, int cap)
 {
     int64_t cnt = 0;
     const int cm = shell_cmax<P>(k, cap);
-    for (int a = 0; a <= cm; ++a)
-        for (int b = 0; b <= cm; ++b) {
-            int lo = 0, hi = -1;
-            shell_c3_range<P>(k, cap, a, b, lo, hi);
-            if (hi >= lo) cnt += hi - lo + 1;
-        }
+    for (int s = 0; s <= 2 * cm; ++s) {
+        const int a = s <= cm ? s : cm, b = s - a;
+        int lo = 0, hi = -1;
+        shell_c3_range<P>(k, cap, a, b, lo, hi);
+        if (hi >= lo) cnt += (int64_t)(hi - lo + 1) * (s <= cm ? s + 1 : 2 * cm - s + 1);
+    }
     return cnt;
 }
 // Number of base tiles band_tile keeps at degree n.  For fixed (u1, u2) both
@@ -206,30 +208,30 @@ constexpr int64_t band_tiles(int n)
 template <int P>
 constexpr PlanTable<P> make_plan_table()
 {
-    constexpr int d = 4 * (P - 1);
+    constexpr int dm = Geo<P>::dm, NF = Geo<P>::NF;
     PlanTable<P> t{};
     int64_t o = 0;
-    for (int k = 0; k < P; ++k) {
+    for (int k = 0; k < NF; ++k) {
         t.boff[k] = o;
-        t.blen[k] = k >= 1 ? base_tiles<P>((k + 1) * d) : 0;
+        t.blen[k] = k >= 1 ? base_tiles((k + 1) * dm) : 0;
         o += t.blen[k];
     }
-    for (int k = 0; k < P; ++k) {
+    for (int k = 0; k < NF; ++k) {
         t.foff[k] = o;
-        t.flen[k] = k <= P - 2 ? shell_tiles<P>(k, CAP_NONE) : 0;
+        t.flen[k] = k <= NF - 2 ? shell_tiles<P>(k, CAP_NONE) : 0;
         o += t.flen[k];
     }
-    for (int k = 0; k < P; ++k) {
+    for (int k = 0; k < NF; ++k) {
         t.noff[k] = o;
-        t.nlen[k] = k >= 1 ? band_tiles<P>((k + 1) * d) : 0;
+        t.nlen[k] = k >= 1 ? band_tiles<P>((k + 1) * dm) : 0;
         o += t.nlen[k];
     }
-    for (int k = 0; k < P; ++k) {
+    for (int k = 0; k < NF; ++k) {
         t.hoff[k] = o;
-        t.hlen[k] = k >= 1 && k <= P - 2 ? shell_tiles<P>(k, P * P - 1) : 0;
+        t.hlen[k] = k >= 1 && k <= NF - 2 ? shell_tiles<P>(k, P * P - 1) : 0;
         o += t.hlen[k];
     }
-    for (int k = 0; k < P; ++k) {
+    for (int k = 0; k < NF; ++k) {
         t.gboff[k] = o;
         o += 4 * ((t.blen[k] + 15) / 16);
         t.ngoff[k] = o;
@@ -255,7 +257,7 @@ __host__ __device__ constexpr bool w_in_lds()
 }
 
 // Per persistent workgroup ("slot") of the deep kernel: the W blocks when
-// they do not fit in LDS, two tile boxes for the chain g~^k, and Delta in
+// they do not fit in LDS, two tile boxes for the chain m^k, and Delta in
 // the Cartier-split layout.
 template <int P>
 __host__ __device__ constexpr size_t slot_bytes()
@@ -311,6 +313,7 @@ struct DeepArgs {
     const int32_t *queue;
     int32_t *queue2;  // positions in `queue` of the surfaces the capped chain left undecided
     const uint8_t *gq;
+    const uint8_t *f;  // [batch][35], the quartics (the multiplier m = f~^J is formed from them)
     const uint32_t *plan;
     uint8_t *slots;
     size_t slot_bytes;

@@ -116,6 +116,12 @@ def test_options():
     finally:
         qfs.set_option("height_graph", 1)
     assert qfs.get_option("height_graphs_cached") == 0
+    # the deep chain's multiplier power per prime: J divides p(p-1), 1 <= J <= p-1
+    for p in (3, 5, 7, 11):
+        J = qfs.get_option("chain_power_p%d" % p)
+        assert 1 <= J <= p - 1 and (p * (p - 1)) % J == 0
+    with pytest.raises(qfs.QfsError):
+        qfs.set_option("chain_power_p7", 1)
 
 
 def test_autotune_and_tuning_cache_argument_errors(tmp_path):

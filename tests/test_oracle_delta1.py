@@ -99,3 +99,27 @@ def test_c_tier_equals_integer_tier_on_real_p5_shape():
     want = literal.delta1(literal.poly_from_dense(g, 16), 5)
     got = literal.poly_from_dense(fast.delta1(g, 5, 16), 80)
     assert got == want
+
+
+@pytest.mark.parametrize("p,J,nterms", [(3, 1, 8), (5, 1, 6), (5, 2, 6), (7, 3, 4), (7, 1, 3)])
+def test_delta1_of_g_from_chain_of_f_powers(p, J, nterms):
+    # g = f^(p-1) mod p has the lift g~ = f~^(p-1) + p h, and (g~ + p h)^p = g~^p
+    # mod p^2, so g~^p = m^(p(p-1)/J) mod p^2 for m = f~^J mod p^2 and any J
+    # dividing p(p-1).  Delta_1(g) from that chain (the one the deep kernels
+    # run) must equal Algorithm 1 applied to g.
+    rng = np.random.default_rng(1000 * p + J)
+    for _ in range(2):
+        f = _rand_terms(rng, p, 4, nterms)
+        ft = literal.lift(f, p)
+        g = literal.poly_mod(literal.poly_pow(ft, p - 1), p)
+        m = literal.poly_mod(literal.poly_pow(ft, J), p * p)
+        A = m
+        for _ in range(p * (p - 1) // J - 1):
+            A = literal.poly_mod(literal.poly_mul(A, m), p * p)
+        D = dict(A)
+        for e, c in g.items():
+            pe = tuple(p * x for x in e)
+            D[pe] = (D.get(pe, 0) - c ** p) % (p * p)
+        assert all(c % p == 0 for c in D.values())
+        got = {e: (c // p) % p for e, c in D.items() if (c // p) % p}
+        assert got == literal.delta1(g, p)

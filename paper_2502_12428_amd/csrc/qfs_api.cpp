@@ -244,7 +244,8 @@ int qfs_delta1(int p, int batch, const uint8_t *f, uint8_t *g_out, uint8_t *delt
     }
     s1.present_mask = 1 << pi;
     if ((e = launch_stage1(s1, stream)) != hipSuccess) return hip_fail(e, "stage1");
-    if ((e = launch_gpow(p, s1, gpow_workgroups(batch), stream)) != hipSuccess) return hip_fail(e, "g");
+    if (gpow_needed(p) && (e = launch_gpow(p, s1, gpow_workgroups(batch), stream)) != hipSuccess)
+        return hip_fail(e, "g");
     if ((e = launch_plan(p, (uint32_t *)(w + L.plan[pi]), stream)) != hipSuccess) return hip_fail(e, "plan");
     DeepArgs da{};
     da.mode = MODE_DELTA;
@@ -255,6 +256,7 @@ int qfs_delta1(int p, int batch, const uint8_t *f, uint8_t *g_out, uint8_t *delt
     da.queue = (const int32_t *)(w + L.queue[pi]);
     da.gq = w + L.gq[pi];
     da.f = f;
+    da.g_out = g_out;
     da.plan = (const uint32_t *)(w + L.plan[pi]);
     da.slots = w + L.slots;
     da.slot_bytes = L.slot_stride[pi];
@@ -334,7 +336,8 @@ static int enqueue_height(int batch, const int32_t *p, const uint8_t *f, int bou
     s1.present_mask = mask;
     if ((e = launch_stage1(s1, stream)) != hipSuccess) return hip_fail(e, "stage1");
     for (int i = 0; i < 4; ++i)
-        if (L.present[i] && (e = launch_gpow(kPrimes[i], s1, gpow_wg, stream)) != hipSuccess) return hip_fail(e, "g");
+        if (L.present[i] && gpow_needed(kPrimes[i]) && (e = launch_gpow(kPrimes[i], s1, gpow_wg, stream)) != hipSuccess)
+            return hip_fail(e, "g");
     prof.mark(0);
     for (int i = 0; i < 4; ++i) {
         if (!L.present[i]) continue;

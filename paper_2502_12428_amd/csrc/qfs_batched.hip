@@ -171,6 +171,17 @@ __global__ __launch_bounds__(256) void k_gpow(Stage1Args a)
     }
 }
 
+bool gpow_needed(int p)
+{
+    switch (p) {
+    case 3: return !g_from_chain<3>();
+    case 5: return !g_from_chain<5>();
+    case 7: return !g_from_chain<7>();
+    case 11: return !g_from_chain<11>();
+    }
+    return true;
+}
+
 hipError_t launch_gpow(int p, const Stage1Args &a, int nwg, hipStream_t s)
 {
     if (a.batch <= 0 || nwg <= 0) return hipSuccess;
@@ -286,7 +297,10 @@ hipError_t launch_plan(int p, uint32_t *plan, hipStream_t s)
 #ifndef QFS_DEEP_PF
 #define QFS_DEEP_PF 4
 #endif
-constexpr int DEEP_NT = QFS_DEEP_NT, DEEP_NW = DEEP_NT / 64, DEEP_NB = 4, DEEP_PF = QFS_DEEP_PF;
+#ifndef QFS_DEEP_NB
+#define QFS_DEEP_NB 4
+#endif
+constexpr int DEEP_NT = QFS_DEEP_NT, DEEP_NW = DEEP_NT / 64, DEEP_NB = QFS_DEEP_NB, DEEP_PF = QFS_DEEP_PF;
 
 template <int P>
 __constant__ DeltaTableX<P> kDX = make_delta_table_x<P>();
@@ -642,6 +656,22 @@ __device__ int theta_test_box(const uint8_t *dbox, const uint8_t *a, int *red)
     return block_sum((int)(part % P), red) % P;
 }
 
+// g = A mod p for the chain link A = f~^(p-1) mod p^2 in a tile box, into g_l
+// (LDS, CNS order) and, if given, out.
+template <int P>
+__device__ void g_from_box(const uint8_t *A, uint8_t *g_l, uint8_t *out)
+{
+    constexpr int d = 4 * (P - 1), LG = (int)num_mono(d);
+    for (int r = threadIdx.x; r < LG; r += blockDim.x) {
+        int x1, x2, x3, x4;
+        cns_unrank(d, r, x1, x2, x3, x4);
+        const uint8_t v =
+            (uint8_t)(gload1(A + box_tile<P>(x1 >> 1, x2 >> 1, x3 >> 2) * 16 + (x1 & 1) * 8 + (x2 & 1) * 4 + (x3 & 3)) % P);
+        g_l[r] = v;
+        if (out) gstore1(out + r, v);
+    }
+}
+
 // Delta at a position x (degree D) from its tile box.
 template <int P>
 struct BoxDelta {
@@ -655,12 +685,14 @@ struct BoxDelta {
 // The chain A_{k+1} = A_k * m, k = 1..NF-1, into the two tile boxes, from the
 // W blocks and m already in place: in full, or (band) only the super-tiles
 // that the height-2 test depends on, ending in the window of Delta it reads.
-// A_NF ends in buf[(NF-1) & 1].
+// A_NF ends in buf[(NF-1) & 1].  When g_from_chain<P>(), g is read off the
+// link A_{(p-1)/J} into g_l (and g_out) before the last product needs it.
 template <int P>
 __device__ __attribute__((always_inline)) inline void run_chain(bool band, const uint32_t *plan, const uint8_t *m_l,
                                                                const uint8_t *W, uint8_t *buf0, uint8_t *buf1,
                                                                const int *toff_l, const uint32_t *widx_l,
-                                                               const uint32_t *qbox_l, uint16_t *qlist_w, EpiCtx ec)
+                                                               const uint32_t *qbox_l, uint16_t *qlist_w, EpiCtx ec,
+                                                               uint8_t *g_l, uint8_t *g_out)
 {
     constexpr int d = GeoX<P>::dm, NF = GeoX<P>::NF;
     const int wave = uniform(threadIdx.x >> 6);
@@ -689,6 +721,10 @@ __device__ __attribute__((always_inline)) inline void run_chain(bool band, const
             zero_shell<P>(plan + (band ? kPT<P>.hoff[k] : kPT<P>.foff[k]), (int)(band ? kPT<P>.hlen[k] : kPT<P>.flen[k]),
                           Aout);
         __syncthreads();
+        if constexpr (g_from_chain<P>()) {
+            // A_{k+1} = f~^(p-1) mod p^2; the next barrier precedes the last product
+            if (k + 1 == (P - 1) / Geo<P>::J) g_from_box<P>(Aout, g_l, g_out);
+        }
     }
 }
 
@@ -767,7 +803,8 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
         if (pos >= count) break;
         const int qpos = q2 ? a.queue2[pos] : pos;  // position in the first queue
         const int surf = a.queue[qpos];
-        for (int i = tid; i < LG; i += DEEP_NT) g_l[i] = a.gq[(size_t)qpos * LG + i];
+        if constexpr (!g_from_chain<P>())
+            for (int i = tid; i < LG; i += DEEP_NT) g_l[i] = a.gq[(size_t)qpos * LG + i];
         const uint8_t *m_l = g_l;
         if constexpr (L::OWN_M) {
             __shared__ __align__(16) uint8_t f35[48];
@@ -788,7 +825,8 @@ __global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
         ec.g = g_l;
         ec.err = &s_err;
         uint16_t *qlist_w = qlist_l + wave * L::QSTRIDE;
-        run_chain<P>(BAND, a.plan, m_l, W, buf[0], buf[1], toff_l, widx_l, qbox_l, qlist_w, ec);
+        uint8_t *g_out = a.mode == MODE_DELTA && a.g_out ? a.g_out + (size_t)surf * LG : nullptr;
+        run_chain<P>(BAND, a.plan, m_l, W, buf[0], buf[1], toff_l, widx_l, qbox_l, qlist_w, ec, g_l, g_out);
         const bool err = s_err != 0;
 
         if (BAND) {

@@ -154,6 +154,15 @@ constexpr int chain_j()
 {
     return P == 3 ? QFS_CHAIN_J3 : P == 5 ? QFS_CHAIN_J5 : P == 7 ? QFS_CHAIN_J7 : QFS_CHAIN_J11;
 }
+// When J < p-1 divides p-1, A_{(p-1)/J} = f~^(p-1) mod p^2 is a link of the
+// chain and g = f^(p-1) mod p is read off it (every coefficient of degree
+// 4(p-1) <= p^2-1 is formed, also in the capped chain); otherwise g is
+// computed beforehand.
+template <int P>
+constexpr bool g_from_chain()
+{
+    return chain_j<P>() < P - 1 && (P - 1) % chain_j<P>() == 0;
+}
 
 // ---------------------------------------------------------------------------
 // Block-Toeplitz geometry for the matrix-core product C = A * m (m of degree

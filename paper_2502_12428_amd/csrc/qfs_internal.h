@@ -314,6 +314,7 @@ struct DeepArgs {
     int32_t *queue2;  // positions in `queue` of the surfaces the capped chain left undecided
     const uint8_t *gq;
     const uint8_t *f;  // [batch][35], the quartics (the multiplier m = f~^J is formed from them)
+    uint8_t *g_out;    // MODE_DELTA, may be null: g per surface when the chain forms it
     const uint32_t *plan;
     uint8_t *slots;
     size_t slot_bytes;
@@ -324,6 +325,8 @@ hipError_t launch_reset(int32_t *counters, hipStream_t s);
 hipError_t launch_stage1(const Stage1Args &a, hipStream_t s);
 // g = f^(p-1) for the surfaces queued for prime p, on nwg persistent workgroups
 hipError_t launch_gpow(int p, const Stage1Args &a, int nwg, hipStream_t s);
+// whether the deep kernels of prime p take g from launch_gpow (else they read it off their chain)
+bool gpow_needed(int p);
 hipError_t launch_plan(int p, uint32_t *plan, hipStream_t s);
 // band: the capped-chain kernel (MODE_HEIGHT), else the full-chain kernel
 hipError_t launch_deep(int p, bool band, const DeepArgs &a, int nslots, hipStream_t s);

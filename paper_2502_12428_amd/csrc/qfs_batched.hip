@@ -404,6 +404,27 @@ __device__ void zero_shell(const uint32_t *list, int ntiles, uint8_t *A)
     }
 }
 
+// x mod p^2 for an accumulator 0 <= x <= C(4J+3,3) (p^2-1)^2 < 2^24 (a sum of
+// products of two residues below p^2), in five full-rate fp32 operations instead
+// of 32-bit integer multiplies: q = floor(x / p^2) = floor((x + 1/2) / p^2) is
+// the truncation of one fma -- (x + 1/2)/p^2 lies at least 1/(2 p^2) from the
+// integers and the fma's error stays below that on this range (every x is
+// checked on the host) -- and x - q p^2 is an integer below 2^24, exact in fp32.
+// (Multipliers with a larger bound take the integer remainder.)
+template <int P>
+__device__ __attribute__((always_inline)) inline unsigned mod_p2(int x)
+{
+    constexpr int64_t BOUND = num_mono(4 * Geo<P>::J) * (int64_t)(P * P - 1) * (P * P - 1);
+    if constexpr (BOUND < (int64_t)1 << 24) {
+        constexpr float C1 = 1.0f / (float)(P * P), C2 = 0.5f / (float)(P * P);
+        const float xf = (float)x;
+        const float q = __builtin_truncf(__builtin_fmaf(xf, C1, C2));
+        return (unsigned)__builtin_fmaf(-q, (float)(P * P), xf);
+    } else {
+        return (unsigned)x % (unsigned)(P * P);
+    }
+}
+
 struct EpiCtx {
     int mode;
     bool win;         // capped chain: only the window p^2-1-d <= x_i <= p^2-1 is formed and checked
@@ -434,7 +455,7 @@ __device__ __attribute__((always_inline)) inline unsigned epilogue(int c1, int c
             constexpr int E = P2 - 1, LO = E - 4 * (P - 1);
             if (x1 < LO || x1 > E || x2 < LO || x2 > E || x3 < LO || x3 > E || x4 < LO || x4 > E) continue;
         }
-        int val = acc[v] % P2;
+        int val = (int)mod_p2<P>(acc[v]);
         if (j12 && x3 % P == 0) {
             const int bj = ec.g[cns_rank(x2 / P, x3 / P, x4 / P)];
             val -= pow_p_mod_p2<P>(bj);
@@ -628,7 +649,7 @@ __device__ __attribute__((always_inline)) inline void mfma_set(const uint32_t *l
             unsigned packed = 0;
             if (!last) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) packed |= ((unsigned)(acc[s][b][v] % P2) & 255u) << (8 * v);
+                for (int v = 0; v < 4; ++v) packed |= mod_p2<P>(acc[s][b][v]) << (8 * v);
             } else {
                 packed = epilogue<P>(c1 + d1, c2 + d2, c3, kg, acc[s][b], ec);
             }

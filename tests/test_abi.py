@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_2502_12428_amd as qfs
@@ -133,3 +134,21 @@ def test_autotune_and_tuning_cache_argument_errors(tmp_path):
     with pytest.raises(qfs.QfsError):
         qfs.set_option("gpow_per_cu", 0)
     assert qfs.get_option("gpow_per_cu") == 8
+
+
+def test_epilogue_division_is_exact():
+    # The deep kernels' epilogue takes floor(x / p^2) as trunc(fma(x, 1/p^2, 0.5/p^2)) in
+    # fp32 for every accumulator value x <= C(4J+3,3) (p^2-1)^2; check that range exhaustively
+    # (one rounding of the exact x*c1 + c2, which float64 holds exactly here).
+    from math import comb
+    for p in (3, 5, 7, 11):
+        for J in (qfs.get_option("chain_power_p%d" % p),):
+            p2 = p * p
+            bound = comb(4 * J + 3, 3) * (p2 - 1) ** 2
+            if bound >= 1 << 24:
+                continue  # the kernels take the integer remainder there
+            c1 = np.float32(1.0) / np.float32(p2)
+            c2 = np.float32(0.5) / np.float32(p2)
+            x = np.arange(bound + 1, dtype=np.int64)
+            y = (x.astype(np.float64) * np.float64(c1) + np.float64(c2)).astype(np.float32)
+            assert np.array_equal(np.trunc(y).astype(np.int64), x // p2), (p, J)

@@ -35,11 +35,11 @@ INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix peak, 5.0 POP/s
 TRAFFIC_SOURCES = ("qfs_batched.hip", "qfs_device.h", "qfs_common.h", "qfs_internal.h")
 TRAFFIC = {
     "workload": "p7_batch65536",
-    "sources_sha256": "12267f0b329faaf834c703cd1171738c50e7e006e300c6f62a48fe67e2e5ab86",
-    "fetch_scale": 524288.0 / 262169.3125, "write_scale": 1.0,
+    "sources_sha256": "cc5e54acffc069e47fab1e083d94449995c70128ba57a4c99479fef1df527273",
+    "fetch_scale": 524288.0 / 262169.2500, "write_scale": 1.0,
     "kernels": {  # kernel name -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
-        "k_deep<7, true>": (26491290.80, 17965394.18),
-        "k_deep<7, false>": (31110177.70, 13173275.15),
+        "k_deep<7, true>": (26438877.34, 17988505.25),
+        "k_deep<7, false>": (30981286.88, 13167565.70),
     },
     "profile": "profiles/k_deep7_p7_batch65536_counters.md",
 }

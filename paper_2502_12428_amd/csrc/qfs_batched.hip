@@ -297,6 +297,10 @@ hipError_t launch_plan(int p, uint32_t *plan, hipStream_t s)
 #ifndef QFS_DEEP_PF
 #define QFS_DEEP_PF 4
 #endif
+// Deep workgroups one compute unit must be able to hold (registers per wave are sized for it).
+#ifndef QFS_DEEP_MINWG
+#define QFS_DEEP_MINWG 1
+#endif
 #ifndef QFS_DEEP_NB
 #define QFS_DEEP_NB 4
 #endif
@@ -756,7 +760,7 @@ __device__ __attribute__((always_inline)) inline void run_chain(bool band, const
 //  !BAND: the full chain g~^p with the Delta_1 epilogue, then (MODE_HEIGHT)
 //    Algorithm 3's theta loop, or (MODE_DELTA) Delta written out in CNS order.
 template <int P, bool BAND>
-__global__ __launch_bounds__(DEEP_NT, 1) void k_deep(DeepArgs a)
+__global__ __launch_bounds__(DEEP_NT, QFS_DEEP_MINWG) void k_deep(DeepArgs a)
 {
     using PR = Prime<P>;
     using X = GeoX<P>;
@@ -1049,7 +1053,7 @@ static size_t plan_bytes_of(int p)
     return 0;
 }
 
-// Persistent workgroups per compute unit for p <= 7 (QFS_DEEP_WGS_PER_CU, 1..8; default 1).
+// The slot area is held to SLOT_AREA_MAX (fewer persistent workgroups beyond it).
 constexpr size_t SLOT_AREA_MAX = (size_t)96 << 30;
 
 BatchLayout make_batch_layout(const bool present[4], int batch, int slots)

@@ -309,6 +309,42 @@ constexpr int DEEP_NT = QFS_DEEP_NT, DEEP_NW = DEEP_NT / 64, DEEP_NB = QFS_DEEP_
 template <int P>
 __constant__ DeltaTableX<P> kDX = make_delta_table_x<P>();
 
+// Geometry of the Cartier split read straight from Delta's tile box.  The
+// rows of every region whose coarse part starts (y1, y2, y3) read only the
+// positions x with floor(x_i / p) = y_i (i = 1..3): a block of NT1 x NT1 x NT3
+// tiles (p consecutive positions meet at most (p+1)/2 tiles of 2 and
+// (p+2)/4 + 1 tiles of 4), staged position-major as W1 x W2 x W3 bytes.  Each
+// block feeds NCH 16-byte chunks, one per column chunk of every region; a wave
+// takes U blocks at a time.
+template <int P>
+struct SplitGeo {
+    static constexpr int NT1 = (P + 1) / 2, NT3 = (P + 2) / 4 + 1, NTB = NT1 * NT1 * NT3;
+    static constexpr int W1 = 2 * NT1, W2 = 2 * NT1, W3 = 4 * NT3, CUBE = W1 * W2 * W3;
+    static constexpr int NCH = ThetaGeo<P>::NCOL / 16;
+    static constexpr int U = NCH >= 64 ? 1 : 64 / NCH;
+    static constexpr int NL = (U * NTB + 63) / 64;  // tile loads per lane and group of U blocks
+    static constexpr int STAGE = U * CUBE;          // LDS bytes per wave
+    static constexpr int NCUBE = (int)num_mono(4 * (P - 1));
+};
+// The coarse blocks (y1, y2, y3), y1 + y2 + y3 <= 4(p-1), packed 8 bits each.
+template <int P>
+struct CubeTable {
+    uint32_t c[SplitGeo<P>::NCUBE];
+};
+template <int P>
+constexpr CubeTable<P> make_cube_table()
+{
+    CubeTable<P> t{};
+    constexpr int d = 4 * (P - 1);
+    int n = 0;
+    for (int y1 = 0; y1 <= d; ++y1)
+        for (int y2 = 0; y1 + y2 <= d; ++y2)
+            for (int y3 = 0; y1 + y2 + y3 <= d; ++y3) t.c[n++] = (uint32_t)y1 | ((uint32_t)y2 << 8) | ((uint32_t)y3 << 16);
+    return t;
+}
+template <int P>
+__constant__ CubeTable<P> kCube = make_cube_table<P>();
+
 template <int P>
 struct DeepLds {
     using X = GeoX<P>;
@@ -331,8 +367,11 @@ struct DeepLds {
     static constexpr int off_qlist = off_qbox + 16 * X::NQX;
     static constexpr int QSTRIDE = X::NQX + DEEP_PF;  // a wave's needed-quad list, padded
     static constexpr int off_red = off_qlist + ((2 * QSTRIDE * (DEEP_NT / 64) + 15) / 16 * 16);
-    static constexpr int off_sums = off_red + 4 * 64;
-    static constexpr int bytes = off_sums + 4 * LGA;
+    static constexpr int off_sig = off_red + 4 * 64;  // the Cartier split's column table
+    static constexpr int off_sums = off_sig + (ThetaGeo<P>::NCOL * 2 + 15) / 16 * 16;
+    // theta's sums, or (not at the same time) the Cartier split's staging blocks
+    static constexpr int SUMS = 4 * LGA > DEEP_NW * SplitGeo<P>::STAGE ? 4 * LGA : DEEP_NW * SplitGeo<P>::STAGE;
+    static constexpr int bytes = off_sums + SUMS;
 };
 
 template <int P>
@@ -697,6 +736,132 @@ __device__ void g_from_box(const uint8_t *A, uint8_t *g_l, uint8_t *out)
     }
 }
 
+// Delta in the Cartier-split layout dl (global) from its tile box.  A wave
+// takes groups of U coarse blocks (SplitGeo); it keeps the tile loads of the
+// next SPLIT_DEPTH - 1 groups in flight in registers, stages one group's tiles
+// position-major in its LDS stage, and assembles the group's chunks there.  A
+// lane always builds the same column chunk (region j, columns 16m..16m+15) of
+// row y = (y1, y2, y3, d - j - y1 - y2 - y3); in the staged block the byte of
+// column sigma lies at base(p y mod T) + lin(sigma), so the lane keeps its 16
+// lin(sigma) and adds one base per block.  stage: DEEP_NW * STAGE bytes of LDS;
+// sig_l: the column table (LDS).  A wave's LDS operations complete in issue
+// order, so the stage needs only a compiler barrier between its writes and
+// reads (a memory fence would also wait for the prefetched tile loads).
+constexpr int SPLIT_DEPTH = 4;
+template <int P>
+__device__ void cartier_split_box(const uint8_t *__restrict__ dbox, uint8_t *dl, uint8_t *stage, const uint16_t *sig_l)
+{
+    using TG = ThetaGeo<P>;
+    using SG = SplitGeo<P>;
+    using X = GeoX<P>;
+    constexpr int d = TG::d, NJ = TG::J, NCUBE = SG::NCUBE;
+    constexpr int NT1 = SG::NT1, NT3 = SG::NT3, NTB = SG::NTB, U = SG::U, NL = SG::NL;
+    constexpr int W2 = SG::W2, W3 = SG::W3, CUBE = SG::CUBE;
+    constexpr int KPL = (U * SG::NCH + 63) / 64;  // chunks per lane and group
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint8_t *st = stage + wave * SG::STAGE;
+    // the tiles of the U blocks from coarse index t0 into registers
+    auto load_group = [&](int t0, v4u *v) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const int i = lane + 64 * l, u = i / NTB, r = i % NTB;
+            v[l] = v4u{0, 0, 0, 0};
+            if (u < U && t0 + u < NCUBE) {
+                const uint32_t cb = kCube<P>.c[t0 + u];
+                const int c1 = ((P * (int)(cb & 255u)) >> 1) + r / (NT1 * NT3),
+                          c2 = ((P * (int)((cb >> 8) & 255u)) >> 1) + (r / NT3) % NT1,
+                          c3 = ((P * (int)(cb >> 16)) >> 2) + r % NT3;
+                if (c1 <= X::C1 && c2 <= X::C2 && c3 < X::C3) v[l] = gload16u(dbox + box_tile<P>(c1, c2, c3) * 16);
+            }
+        }
+    };
+    // this lane's chunks: block u of the group, region j, column chunk m, and the
+    // staged offsets lin(sigma) of its 16 columns (two per word; pad: bit q set)
+    int ku[KPL], kj[KPL], km[KPL], krs[KPL];
+    int64_t kro[KPL];
+    unsigned klin[KPL][8], kpad[KPL];
+#pragma unroll
+    for (int c = 0; c < KPL; ++c) {
+        const int k = lane + 64 * c, kc = k % SG::NCH;
+        ku[c] = k < U * SG::NCH ? k / SG::NCH : U;  // U: no chunk
+        int j = 0;
+#pragma unroll
+        for (int r = 1; r < NJ; ++r)
+            if (kc * 16 >= TG::col_off(r)) j = r;
+        int cb = 0;
+        krs[c] = 0;
+        kro[c] = 0;
+#pragma unroll
+        for (int r = 0; r < NJ; ++r)
+            if (j == r) {
+                cb = TG::col_off(r);
+                krs[c] = TG::rs(r);
+                kro[c] = TG::region_off(r);
+            }
+        kj[c] = j;
+        km[c] = kc - cb / 16;
+        kpad[c] = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const unsigned sv = sig_l[cb + 16 * km[c] + q];
+            const unsigned lin = sv == 0xFFFFu ? 0u
+                                               : ((sv & 15u) * W2 + ((sv >> 4) & 15u)) * W3 + ((sv >> 8) & 15u);
+            if (sv == 0xFFFFu) kpad[c] |= 1u << q;
+            if (q & 1)
+                klin[c][q >> 1] |= lin << 16;
+            else
+                klin[c][q >> 1] = lin;
+        }
+    }
+    const int stride = nw * U;
+    v4u ring[SPLIT_DEPTH][NL];
+#pragma unroll
+    for (int s = 0; s < SPLIT_DEPTH; ++s)
+        if (wave * U + s * stride < NCUBE) load_group(wave * U + s * stride, ring[s]);
+    for (int tb = wave * U; tb < NCUBE; tb += SPLIT_DEPTH * stride) {
+#pragma unroll
+        for (int s = 0; s < SPLIT_DEPTH; ++s) {
+            const int t0 = tb + s * stride;
+            if (t0 >= NCUBE) break;
+            // tile (i1, i2, i3) of block u: its rows (s1, s2) of 4 bytes to positions (2 i1 + s1, 2 i2 + s2, 4 i3..4 i3 + 3)
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                const int i = lane + 64 * l;
+                if (i < U * NTB) {
+                    const int u = i / NTB, r = i % NTB;
+                    const int i1 = r / (NT1 * NT3), i2 = (r / NT3) % NT1, i3 = r % NT3;
+                    uint8_t *blk = st + u * CUBE + 4 * i3;
+                    *(unsigned *)(blk + ((2 * i1) * W2 + 2 * i2) * W3) = ring[s][l].x;
+                    *(unsigned *)(blk + ((2 * i1) * W2 + 2 * i2 + 1) * W3) = ring[s][l].y;
+                    *(unsigned *)(blk + ((2 * i1 + 1) * W2 + 2 * i2) * W3) = ring[s][l].z;
+                    *(unsigned *)(blk + ((2 * i1 + 1) * W2 + 2 * i2 + 1) * W3) = ring[s][l].w;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (t0 + SPLIT_DEPTH * stride < NCUBE) load_group(t0 + SPLIT_DEPTH * stride, ring[s]);
+#pragma unroll
+            for (int c = 0; c < KPL; ++c) {
+                const int u = ku[c];
+                if (u >= U || t0 + u >= NCUBE) continue;
+                const uint32_t cb = kCube<P>.c[t0 + u];
+                const int y1 = (int)(cb & 255u), y2 = (int)((cb >> 8) & 255u), y3 = (int)(cb >> 16);
+                const int y4 = d - kj[c] - y1 - y2 - y3;
+                if (y4 < 0) continue;
+                const uint8_t *blk = st + u * CUBE + ((((P * y1) & 1) * W2 + ((P * y2) & 1)) * W3 + ((P * y3) & 3));
+                unsigned w[4] = {0, 0, 0, 0};
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    unsigned b = blk[(klin[c][q >> 1] >> (16 * (q & 1))) & 0xFFFFu];
+                    if ((kpad[c] >> q) & 1u) b = 0;
+                    w[q >> 2] |= b << (8 * (q & 3));
+                }
+                gstore16(dl + kro[c] + (int64_t)cns_rank(y2, y3, y4) * krs[c] + 16 * km[c], v4u{w[0], w[1], w[2], w[3]});
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
 // Delta at a position x (degree D) from its tile box.
 template <int P>
 struct BoxDelta {
@@ -775,6 +940,7 @@ __global__ __launch_bounds__(DEEP_NT, QFS_DEEP_MINWG) void k_deep(DeepArgs a)
     uint16_t *qlist_l = (uint16_t *)(lds + L::off_qlist);
     int *red = (int *)(lds + L::off_red);
     uint32_t *sums = (uint32_t *)(lds + L::off_sums);
+    uint16_t *sig_l = (uint16_t *)(lds + L::off_sig);
     __shared__ int s_pos, s_err;
 
     const int tid = threadIdx.x, wave = uniform(tid >> 6);
@@ -799,6 +965,8 @@ __global__ __launch_bounds__(DEEP_NT, QFS_DEEP_MINWG) void k_deep(DeepArgs a)
         toff_l[X::NVXP + tid] = 0;
         widx_l[2 * (X::NVXP + tid)] = widx_l[2 * (X::NVXP + tid) + 1] = (uint32_t)X::NV | ((uint32_t)X::NV << 16);
     }
+    if (!BAND)
+        for (int i = tid; i < ThetaGeo<P>::NCOL; i += DEEP_NT) sig_l[i] = kTT<P>.sig[i];
     for (int i = tid; i < X::NQX; i += DEEP_NT) {
         qbox_l[4 * i] = kDX<P>.qmin[i];
         qbox_l[4 * i + 1] = (uint32_t)kDX<P>.qwmax[i];
@@ -879,29 +1047,25 @@ __global__ __launch_bounds__(DEEP_NT, QFS_DEEP_MINWG) void k_deep(DeepArgs a)
             if (tid == 0) a.heights[surf] = -5;
             continue;
         }
-        // Algorithm 3's loop: the test reads c(theta(a)) only; theta(a) in full
-        // is needed only when the surface goes on to the next h.  Surfaces from
-        // the second queue are known to fail the first test.
+        // Algorithm 3's loop: the test at h reads c(theta(a)) only, a = theta^(h-2)(g);
+        // theta(a) in full is formed when the surface goes on to the next h.
+        // Surfaces from the second queue are known to fail the test at h = 2.
         const uint8_t *dbox = buf[(X::NF - 1) & 1];
         int h = 0;
-        bool split = false;
-        for (int hh = 2; hh <= a.bound; ++hh) {
-            if (hh > 2 || !q2) {
-                const int t = theta_test_box<P>(dbox, g_l, red);
-                if (t != 0) {
+        const bool h2 = !q2 && theta_test_box<P>(dbox, g_l, red) != 0;
+        if (h2) h = 2;
+        if (!h2 && a.bound > 2) {
+            cartier_split_box<P>(dbox, dl, (uint8_t *)sums, sig_l);
+            for (int hh = 3; hh <= a.bound; ++hh) {
+                build_aperm<P>(g_l, aperm);
+                __syncthreads();
+                theta_full<P>(dl, aperm, sums, g_l);
+                __syncthreads();
+                if (theta_test_box<P>(dbox, g_l, red) != 0) {
                     h = hh;
                     break;
                 }
             }
-            if (hh == a.bound) break;
-            if (!split) {
-                cartier_split<P>(BoxDelta<P>{dbox}, dl);
-                split = true;
-            }
-            build_aperm<P>(g_l, aperm);
-            __syncthreads();
-            theta_full<P>(dl, aperm, sums, g_l);
-            __syncthreads();
         }
         if (tid == 0) a.heights[surf] = h;
     }

@@ -138,6 +138,7 @@ def main():
     ap.add_argument("--cpu-sample-single", type=int, default=48)
     ap.add_argument("--plain-sample", type=int, default=48)
     ap.add_argument("--no-baselines", action="store_true")
+    ap.add_argument("--no-reduced", action="store_true", help="skip timing qfs_height_reduced")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before the timed region, copy this many MiB device-to-device once: a plain copy "
                          "kernel of known size whose memory counters scale the profiler's byte counts")
@@ -210,6 +211,24 @@ def main():
         graph = {"ms_per_step": 1e3 * (tg1 - tg0) / args.steps, "value": B * args.steps / (tg1 - tg0),
                  "graphs_cached": qfs.get_option("height_graphs_cached"),
                  "agrees": bool(np.array_equal(out_h.cpu().numpy(), heights))}
+
+    # the reduced form of Algorithm 3 (qfs_height_reduced: no g~^p, one 35 x 35
+    # linear map per deep surface), timed the same way after the main region
+    reduced = None
+    if not args.no_reduced:
+        out_r = torch.empty(B, dtype=torch.int32, device="cuda")
+        for _ in range(max(args.warmup, 1)):
+            qfs.height_reduced(f, pt, max_p=p, workspace=ws, out=out_r)
+        torch.cuda.synchronize()
+        tr0 = time.perf_counter()
+        for _ in range(args.steps):
+            qfs.height_reduced(f, pt, max_p=p, workspace=ws, out=out_r)
+        torch.cuda.synchronize()
+        tr1 = time.perf_counter()
+        reduced = {"ms_per_step": 1e3 * (tr1 - tr0) / args.steps, "value": B * args.steps / (tr1 - tr0),
+                   "unit": "quartics/s", "agrees": bool(np.array_equal(out_r.cpu().numpy(), heights)),
+                   "method": "h from <hvec, N^(k-1) f>, N[r', r] = (Delta_1(f) f^(p-2))[p r' + e - r]; "
+                             "no int8 matrix cores (not the headline path)"}
 
     parity = "unchecked"
     gold = os.path.join(ROOT, "tests", "golden", "heights_%s.npz" % args.workload)
@@ -310,6 +329,7 @@ def main():
         "stage_ms_per_step": per_call,
         "per_prime": per_prime,
         "graph_replay": graph,
+        "reduced_form": reduced,
     }
 
     if not args.no_baselines:

@@ -167,6 +167,26 @@ int qfs_height_plain(int p, int batch, const uint8_t *f, int bound, int32_t *hei
                      void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * qfs_height_reduced: the same heights as qfs_height (Algorithm 3, bound
+ * <= 10) from a reduced form that needs neither g~^p nor Delta_1(g).  With
+ * D = Delta_1(f) (Algorithm 1 applied to f) and H = f^(p-2) mod p, the
+ * binomial theorem mod p^2 gives Delta_1(f^(p-1)) = phi(Q) - D phi(H) mod p
+ * (phi multiplies exponents by p); the splitting u of Algorithm 2 is
+ * p^-1-linear, so along Algorithm 3's loop theta^(k-1)(g) = H v_k for quartics
+ * v_1 = f, v_(k+1) = -u(D H v_k), and the test reads c(H v_k).  Not an
+ * algorithm of the paper; it is checked against the paper's Algorithms 1-3
+ * by the oracle tests and against qfs_height by the GPU tests.  Fedder's test
+ * (Section 2.2) runs first for every surface, as in qfs_height; one
+ * workgroup per remaining surface forms H and D in LDS and iterates.
+ * Arguments, layouts and errors as qfs_height; the workspace is
+ * qfs_height_reduced_workspace_bytes(batch, max_p) bytes (counters and one
+ * queue per prime), caller-owned, 256-byte aligned.  No graph capture.
+ * ---------------------------------------------------------------------- */
+size_t qfs_height_reduced_workspace_bytes(int batch, int max_p);
+int qfs_height_reduced(int batch, const int32_t *p, const uint8_t *f, int bound, int max_p, int32_t *heights,
+                       void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Stage timing (diagnostics).  While enabled, every qfs_height call records
  * hipEvents on its stream around its stages; qfs_profile_collect waits for
  * the recorded events, writes the summed milliseconds per stage into

@@ -34,6 +34,7 @@ EXPORTS = (
     "qfs_num_monomials", "qfs_monomial_rank", "qfs_monomial_unrank", "qfs_len_g", "qfs_len_delta",
     "qfs_delta1_workspace_bytes", "qfs_delta1", "qfs_theta_workspace_bytes", "qfs_theta",
     "qfs_height_workspace_bytes", "qfs_height", "qfs_height_plain_workspace_bytes", "qfs_height_plain",
+    "qfs_height_reduced_workspace_bytes", "qfs_height_reduced",
     "qfs_profile_enable", "qfs_profile_collect", "qfs_mfma_per_surface", "qfs_set_option", "qfs_get_option",
     "qfs_autotune", "qfs_load_tuning", "qfs_last_error", "qfs_shutdown",
 )
@@ -71,6 +72,8 @@ def lib():
     L.qfs_height.argtypes, L.qfs_height.restype = [i32, vp, vp, i32, i32, vp, vp, sz, vp], i32
     L.qfs_height_plain_workspace_bytes.argtypes, L.qfs_height_plain_workspace_bytes.restype = [i32], sz
     L.qfs_height_plain.argtypes, L.qfs_height_plain.restype = [i32, i32, vp, i32, vp, vp, sz, vp], i32
+    L.qfs_height_reduced_workspace_bytes.argtypes, L.qfs_height_reduced_workspace_bytes.restype = [i32, i32], sz
+    L.qfs_height_reduced.argtypes, L.qfs_height_reduced.restype = [i32, vp, vp, i32, i32, vp, vp, sz, vp], i32
     L.qfs_profile_enable.argtypes, L.qfs_profile_enable.restype = [i32], i32
     L.qfs_profile_collect.argtypes, L.qfs_profile_collect.restype = [vp, vp], i32
     L.qfs_mfma_per_surface.argtypes, L.qfs_mfma_per_surface.restype = [i32, i32], i64
@@ -194,6 +197,30 @@ def height(f, p, bound=10, max_p=None, workspace=None, out=None):
     ws = (workspace or _ws).get(lib().qfs_height_workspace_bytes(B, int(max_p)), f.device)
     _check(lib().qfs_height(B, _ptr(pt), _ptr(f), int(bound), int(max_p), _ptr(h), _ptr(ws), ws.numel(),
                             _stream()))
+    return h
+
+
+def height_reduced(f, p, bound=10, max_p=None, workspace=None, out=None):
+    """Heights from the reduced form (qfs_height_reduced): the same values as height()."""
+    f = _device_u8(f, "f")
+    B = f.shape[0]
+    if isinstance(p, torch.Tensor):
+        pt = p.to(device=f.device, dtype=torch.int32).contiguous()
+        if max_p is None:
+            max_p = int(pt.max().item()) if B else 3
+            max_p = min([q for q in PRIMES if q >= max_p] or [11])
+    else:
+        pt = torch.full((B,), int(p), dtype=torch.int32, device=f.device)
+        max_p = max_p or int(p)
+    if out is None:
+        h = torch.empty(B, dtype=torch.int32, device=f.device)
+    else:
+        if out.dtype != torch.int32 or out.device != f.device or out.numel() != B or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32 tensor of %d elements on %s" % (B, f.device))
+        h = out
+    ws = (workspace or _ws).get(lib().qfs_height_reduced_workspace_bytes(B, int(max_p)), f.device)
+    _check(lib().qfs_height_reduced(B, _ptr(pt), _ptr(f), int(bound), int(max_p), _ptr(h), _ptr(ws), ws.numel(),
+                                    _stream()))
     return h
 
 

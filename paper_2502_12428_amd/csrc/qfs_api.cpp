@@ -646,6 +646,80 @@ int qfs_load_tuning(const char *cache_path, int max_p)
 // ---------------------------------------------------------------------------
 size_t qfs_height_plain_workspace_bytes(int p) { return supported(p) ? plain_scratch_bytes(p) : 0; }
 
+// ---------------------------------------------------------------------------
+// Reduced heights: stage 1 (Fedder's test and the deep queues), then one
+// persistent kernel per present prime.
+// ---------------------------------------------------------------------------
+static size_t reduced_layout(const bool present[4], int batch, size_t queue[4])
+{
+    size_t off = align256(CNT_WORDS * sizeof(int32_t));
+    for (int i = 0; i < 4; ++i) {
+        queue[i] = 0;
+        if (!present[i]) continue;
+        queue[i] = off;
+        off += align256((size_t)batch * sizeof(int32_t));
+    }
+    return off;
+}
+
+size_t qfs_height_reduced_workspace_bytes(int batch, int max_p)
+{
+    if (batch < 0 || max_p < 3 || max_p > 11) return 0;
+    bool present[4];
+    present_upto(max_p, present);
+    size_t q[4];
+    return reduced_layout(present, batch, q);
+}
+
+int qfs_height_reduced(int batch, const int32_t *p, const uint8_t *f, int bound, int max_p, int32_t *heights,
+                       void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    g_err[0] = 0;
+    if (batch < 0) return fail(QFS_EINVAL, "qfs_height_reduced: batch=%d < 0", batch);
+    if (bound < 1 || bound > 10) return fail(QFS_EINVAL, "qfs_height_reduced: bound=%d outside 1..10", bound);
+    if (max_p < 3 || max_p > 11 || !supported(max_p))
+        return fail(QFS_EUNSUPPORTED, "qfs_height_reduced: max_p=%d not in {3,5,7,11}", max_p);
+    if (batch == 0) return QFS_OK;
+    if (!p || !f || !heights || !ws) return fail(QFS_EINVAL, "qfs_height_reduced: null pointer argument");
+    if (!aligned(ws)) return fail(QFS_EINVAL, "qfs_height_reduced: workspace not 256-byte aligned");
+    const int ncu = device_cus();
+    if (ncu <= 0) return fail(QFS_EDEVICE, "qfs_height_reduced: no HIP device");
+    bool present[4];
+    present_upto(max_p, present);
+    size_t qoff[4];
+    const size_t need = reduced_layout(present, batch, qoff);
+    if (ws_bytes < need)
+        return fail(QFS_ENOMEM, "qfs_height_reduced: workspace %zu bytes < %zu needed", ws_bytes, need);
+    uint8_t *w = (uint8_t *)ws;
+    int32_t *counters = (int32_t *)w;
+    hipError_t e;
+    if ((e = launch_reset(counters, stream)) != hipSuccess) return hip_fail(e, "reset");
+    Stage1Args s1{};
+    s1.batch = batch;
+    s1.mode = MODE_HEIGHT;
+    s1.fixed_p = 0;
+    s1.bound = bound;
+    s1.p = p;
+    s1.f = f;
+    s1.heights = heights;
+    s1.counters = counters;
+    int mask = 0;
+    for (int i = 0; i < 4; ++i) {
+        s1.queue[i] = present[i] ? (int32_t *)(w + qoff[i]) : nullptr;
+        s1.gq[i] = nullptr;
+        if (present[i]) mask |= 1 << i;
+    }
+    s1.present_mask = mask;
+    if ((e = launch_stage1(s1, stream)) != hipSuccess) return hip_fail(e, "stage1");
+    for (int i = 0; i < 4; ++i) {
+        if (!present[i]) continue;
+        // LDS per workgroup grows with p; 8 per compute unit at p <= 7, 3 at p = 11
+        const int nwg = ncu * (kPrimes[i] == 11 ? 3 : 8);
+        if ((e = launch_reduced(kPrimes[i], s1, nwg, stream)) != hipSuccess) return hip_fail(e, "reduced");
+    }
+    return QFS_OK;
+}
+
 int qfs_height_plain(int p, int batch, const uint8_t *f, int bound, int32_t *heights, void *ws, size_t ws_bytes,
                      hipStream_t stream)
 {

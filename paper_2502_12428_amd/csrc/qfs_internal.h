@@ -327,6 +327,8 @@ hipError_t launch_stage1(const Stage1Args &a, hipStream_t s);
 hipError_t launch_gpow(int p, const Stage1Args &a, int nwg, hipStream_t s);
 // whether the deep kernels of prime p take g from launch_gpow (else they read it off their chain)
 bool gpow_needed(int p);
+// qfs_height_reduced's per-surface kernel over the deep queue of prime p (nwg persistent workgroups)
+hipError_t launch_reduced(int p, const Stage1Args &a, int nwg, hipStream_t s);
 hipError_t launch_plan(int p, uint32_t *plan, hipStream_t s);
 // band: the capped-chain kernel (MODE_HEIGHT), else the full-chain kernel
 hipError_t launch_deep(int p, bool band, const DeepArgs &a, int nslots, hipStream_t s);

@@ -152,3 +152,15 @@ def test_epilogue_division_is_exact():
             x = np.arange(bound + 1, dtype=np.int64)
             y = (x.astype(np.float64) * np.float64(c1) + np.float64(c2)).astype(np.float32)
             assert np.array_equal(np.trunc(y).astype(np.int64), x // p2), (p, J)
+
+
+def test_height_reduced_argument_errors():
+    L = qfs.lib()
+    assert L.qfs_height_reduced_workspace_bytes(-1, 7) == 0
+    assert L.qfs_height_reduced_workspace_bytes(16, 13) == 0
+    assert L.qfs_height_reduced_workspace_bytes(16, 7) >= 256 + 3 * 256
+    assert L.qfs_height_reduced(-1, None, None, 10, 7, None, None, 0, None) == qfs.QFS_EINVAL
+    assert L.qfs_height_reduced(4, None, None, 11, 7, None, None, 0, None) == qfs.QFS_EINVAL
+    assert L.qfs_height_reduced(4, None, None, 10, 13, None, None, 0, None) == qfs.QFS_EUNSUPPORTED
+    assert L.qfs_height_reduced(4, None, None, 10, 7, None, None, 0, None) == qfs.QFS_EINVAL
+    assert L.qfs_height_reduced(0, None, None, 10, 7, None, None, 0, None) == qfs.QFS_OK

@@ -159,6 +159,35 @@ def test_height_workloads_against_oracle(qfs, name):
         bad.size, len(H), bad[:5], got[bad[:5]], H[bad[:5]])
 
 
+@pytest.mark.parametrize("name", ["p5_single", "p7_single", "p5_batch8192", "p7_batch65536", "mixed4096"])
+def test_height_reduced_workloads_against_oracle(qfs, name):
+    # the reduced form (one 35 x 35 linear map per deep surface) against the
+    # heights Algorithm 3's C tier stored for the workload
+    F, P, H = load_golden(name)
+    say("height_reduced workload %s (%d surfaces)" % (name, len(H)))
+    got = host(qfs.height_reduced(dev(F), dev(P), max_p=int(P.max())))
+    bad = np.flatnonzero(got != H)
+    assert bad.size == 0, "%d of %d heights differ; first %s: got %s want %s" % (
+        bad.size, len(H), bad[:5], got[bad[:5]], H[bad[:5]])
+
+
+@pytest.mark.parametrize("p", [5, 7, 11])
+def test_height_reduced_paper_tables(qfs, p):
+    F, H = paper_rows(p)
+    say("height_reduced paper table p=%d" % p)
+    assert host(qfs.height_reduced(dev(F), p)).tolist() == H.tolist()
+
+
+@pytest.mark.parametrize("bound", [1, 2, 3, 5])
+def test_height_reduced_bounds_match_height(qfs, bound):
+    # every bound gives the heights of Algorithm 3 cut at that bound
+    F, P, H = load_golden("mixed4096")
+    want = np.where((H >= 1) & (H <= bound), H, 0)
+    say("height_reduced bound %d on mixed4096" % bound)
+    got = host(qfs.height_reduced(dev(F), dev(P), bound=bound, max_p=int(P.max())))
+    assert np.array_equal(got, want)
+
+
 @pytest.mark.parametrize("name", ["p5_single", "p7_single"])
 def test_height_plain_against_oracle(qfs, name):
     F, P, H = load_golden(name)

@@ -22,27 +22,34 @@ __host__ __device__ constexpr int64_t num_mono(int deg)
     return deg < 0 ? 0 : (int64_t)(deg + 3) * (deg + 2) * (deg + 1) / 6;
 }
 
+// Ranks and degrees here stay far below the 32-bit limits ((m+2)(m+1)m < 2^32
+// for m <= 1600; the largest degree used is 4p(p-1) = 440), so the arithmetic
+// is done in 32 bits.
+__host__ __device__ inline unsigned tet3(unsigned m) { return (m + 2) * (m + 1) * m / 6u; }  // C(m+2,3)
+__host__ __device__ inline unsigned tri2(unsigned m) { return (m + 1) * m / 2u; }            // C(m+1,2)
+
 __host__ __device__ inline int64_t cns_rank(int e2, int e3, int e4)
 {
-    int64_t m1 = e2 + e3 + e4, m2 = e3 + e4;
-    return (m1 + 2) * (m1 + 1) * m1 / 6 + (m2 + 1) * m2 / 2 + e4;
+    const unsigned m1 = (unsigned)(e2 + e3 + e4), m2 = (unsigned)(e3 + e4);
+    return (int64_t)(tet3(m1) + tri2(m2) + (unsigned)e4);
 }
 
 // Inverse of cns_rank for degree n: exponents (e1,e2,e3,e4) of position r.
-__host__ __device__ inline void cns_unrank(int n, int64_t r, int &e1, int &e2, int &e3, int &e4)
+__host__ __device__ inline void cns_unrank(int n, int64_t r64, int &e1, int &e2, int &e3, int &e4)
 {
+    const unsigned r = (unsigned)r64;
     // m1 = e2+e3+e4 is the largest m with C(m+2,3) <= r
-    int m1 = (int)cbrtf((float)(6 * r + 1));
+    int m1 = (int)cbrtf((float)(6.0f * (float)r + 1.0f));
     if (m1 > n) m1 = n;
-    while (m1 > 0 && (int64_t)(m1 + 2) * (m1 + 1) * m1 / 6 > r) --m1;
-    while (m1 < n && (int64_t)(m1 + 3) * (m1 + 2) * (m1 + 1) / 6 <= r) ++m1;
-    int64_t r1 = r - (int64_t)(m1 + 2) * (m1 + 1) * m1 / 6;
+    while (m1 > 0 && tet3((unsigned)m1) > r) --m1;
+    while (m1 < n && tet3((unsigned)m1 + 1u) <= r) ++m1;
+    const unsigned r1 = r - tet3((unsigned)m1);
     // m2 = e3+e4 is the largest m <= m1 with C(m+1,2) <= r1
-    int m2 = (int)sqrtf((float)(2 * r1 + 1));
+    int m2 = (int)sqrtf((float)(2u * r1 + 1u));
     if (m2 > m1) m2 = m1;
-    while (m2 > 0 && (int64_t)(m2 + 1) * m2 / 2 > r1) --m2;
-    while (m2 < m1 && (int64_t)(m2 + 2) * (m2 + 1) / 2 <= r1) ++m2;
-    e4 = (int)(r1 - (int64_t)(m2 + 1) * m2 / 2);
+    while (m2 > 0 && tri2((unsigned)m2) > r1) --m2;
+    while (m2 < m1 && tri2((unsigned)m2 + 1u) <= r1) ++m2;
+    e4 = (int)(r1 - tri2((unsigned)m2));
     e3 = m2 - e4;
     e2 = m1 - m2;
     e1 = n - m1;

@@ -230,6 +230,9 @@ def main():
                    "method": "h from <hvec, N^(k-1) f>, N[r', r] = (Delta_1(f) f^(p-2))[p r' + e - r]; "
                              "no int8 matrix cores (not the headline path)"}
 
+    # the sustained int8 matrix-core rate of this device on a pure MFMA loop
+    peak_measured = qfs.mfma_peak(20000)
+
     parity = "unchecked"
     gold = os.path.join(ROOT, "tests", "golden", "heights_%s.npz" % args.workload)
     if os.path.exists(gold):
@@ -324,6 +327,8 @@ def main():
             "surfaces_per_launch": kd["surfaces"],
             "executed_mfma_tops": kd["executed_mfma_tops"],
             "executed_mfma_frac": kd["executed_mfma_frac"],
+            "peak_measured": peak_measured,
+            "executed_frac_of_measured_peak": kd["executed_mfma_tops"] / peak_measured if peak_measured else None,
             "kernels": kernels,
         },
         "stage_ms_per_step": per_call,

@@ -207,6 +207,15 @@ int qfs_profile_collect(double ms[QFS_PROFILE_STAGES], int *calls);
  * unsupported p or pass. */
 int64_t qfs_mfma_per_surface(int p, int pass);
 
+/* The int8 matrix-core rate this device sustains (TOP/s, two operations per
+ * multiply-add) on a loop of independent v_mfma_i32_16x16x64_i8 on register
+ * operands with no memory traffic, over `iters` iterations (1..10^7) on 8
+ * workgroups per compute unit: the measured ceiling for the deep kernels'
+ * executed-MFMA figure, next to the nominal 5.0 POP/s.  sink: a caller-owned
+ * device int the kernel may write (it does not for these operands).  Waits
+ * for the measurement (hipEvents on `stream`).  Diagnostics only. */
+int qfs_mfma_peak(int iters, int32_t *sink, double *tops, hipStream_t stream);
+
 /* Process-wide options (host strings; affect calls enqueued afterwards).
  *   "height_band" (default 1): qfs_height decides h = 2 with the capped
  *     chain, which forms only the coefficients of Delta_1 that the first

@@ -34,7 +34,7 @@ EXPORTS = (
     "qfs_num_monomials", "qfs_monomial_rank", "qfs_monomial_unrank", "qfs_len_g", "qfs_len_delta",
     "qfs_delta1_workspace_bytes", "qfs_delta1", "qfs_theta_workspace_bytes", "qfs_theta",
     "qfs_height_workspace_bytes", "qfs_height", "qfs_height_plain_workspace_bytes", "qfs_height_plain",
-    "qfs_height_reduced_workspace_bytes", "qfs_height_reduced",
+    "qfs_height_reduced_workspace_bytes", "qfs_height_reduced", "qfs_mfma_peak",
     "qfs_profile_enable", "qfs_profile_collect", "qfs_mfma_per_surface", "qfs_set_option", "qfs_get_option",
     "qfs_autotune", "qfs_load_tuning", "qfs_last_error", "qfs_shutdown",
 )
@@ -74,6 +74,7 @@ def lib():
     L.qfs_height_plain.argtypes, L.qfs_height_plain.restype = [i32, i32, vp, i32, vp, vp, sz, vp], i32
     L.qfs_height_reduced_workspace_bytes.argtypes, L.qfs_height_reduced_workspace_bytes.restype = [i32, i32], sz
     L.qfs_height_reduced.argtypes, L.qfs_height_reduced.restype = [i32, vp, vp, i32, i32, vp, vp, sz, vp], i32
+    L.qfs_mfma_peak.argtypes, L.qfs_mfma_peak.restype = [i32, vp, ctypes.POINTER(ctypes.c_double), vp], i32
     L.qfs_profile_enable.argtypes, L.qfs_profile_enable.restype = [i32], i32
     L.qfs_profile_collect.argtypes, L.qfs_profile_collect.restype = [vp, vp], i32
     L.qfs_mfma_per_surface.argtypes, L.qfs_mfma_per_surface.restype = [i32, i32], i64
@@ -222,6 +223,14 @@ def height_reduced(f, p, bound=10, max_p=None, workspace=None, out=None):
     _check(lib().qfs_height_reduced(B, _ptr(pt), _ptr(f), int(bound), int(max_p), _ptr(h), _ptr(ws), ws.numel(),
                                     _stream()))
     return h
+
+
+def mfma_peak(iters=20000):
+    """Sustained int8 matrix-core rate of this device in TOP/s (qfs_mfma_peak)."""
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    tops = ctypes.c_double(0.0)
+    _check(lib().qfs_mfma_peak(int(iters), _ptr(sink), ctypes.byref(tops), _stream()))
+    return tops.value
 
 
 def autotune(f, p, bound=10, max_p=None, workspace=None, cache_path=None, reps=2):

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqfs.so")
-SOURCES = ["qfs_api.cpp", "qfs_batched.hip", "qfs_theta.hip", "qfs_plain.hip", "qfs_reduced.hip"]
+SOURCES = ["qfs_api.cpp", "qfs_batched.hip", "qfs_theta.hip", "qfs_plain.hip", "qfs_reduced.hip", "qfs_diag.hip"]
 ARCH = os.environ.get("QFS_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

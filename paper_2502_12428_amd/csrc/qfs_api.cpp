@@ -486,6 +486,20 @@ int64_t qfs_mfma_per_surface(int p, int pass)
     return mfma_count(p, pass == 1);
 }
 
+int qfs_mfma_peak(int iters, int32_t *sink, double *tops, hipStream_t stream)
+{
+    g_err[0] = 0;
+    if (iters < 1 || iters > 10000000 || !sink || !tops) return fail(QFS_EINVAL, "qfs_mfma_peak: bad argument");
+    const int ncu = device_cus();
+    if (ncu <= 0) return fail(QFS_EDEVICE, "qfs_mfma_peak: no HIP device");
+    const int nwg = 8 * ncu;
+    float ms = 0.0f;
+    const hipError_t e = mfma_peak(iters, nwg, sink, &ms, stream);
+    if (e != hipSuccess) return hip_fail(e, "mfma peak");
+    *tops = ms > 0.0f ? (double)mfma_peak_ops(iters, nwg) / (ms * 1e-3) / 1e12 : 0.0;
+    return QFS_OK;
+}
+
 int qfs_set_option(const char *name, int64_t value)
 {
     if (!name) return fail(QFS_EINVAL, "qfs_set_option: null name");

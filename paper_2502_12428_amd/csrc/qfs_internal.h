@@ -329,6 +329,9 @@ hipError_t launch_gpow(int p, const Stage1Args &a, int nwg, hipStream_t s);
 bool gpow_needed(int p);
 // qfs_height_reduced's per-surface kernel over the deep queue of prime p (nwg persistent workgroups)
 hipError_t launch_reduced(int p, const Stage1Args &a, int nwg, hipStream_t s);
+// the pure matrix-core loop: times `iters` iterations on nwg workgroups (waits for it), and its operation count
+hipError_t mfma_peak(int iters, int nwg, int *sink, float *ms, hipStream_t s);
+int64_t mfma_peak_ops(int iters, int nwg);
 hipError_t launch_plan(int p, uint32_t *plan, hipStream_t s);
 // band: the capped-chain kernel (MODE_HEIGHT), else the full-chain kernel
 hipError_t launch_deep(int p, bool band, const DeepArgs &a, int nslots, hipStream_t s);

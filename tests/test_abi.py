@@ -164,3 +164,11 @@ def test_height_reduced_argument_errors():
     assert L.qfs_height_reduced(4, None, None, 10, 13, None, None, 0, None) == qfs.QFS_EUNSUPPORTED
     assert L.qfs_height_reduced(4, None, None, 10, 7, None, None, 0, None) == qfs.QFS_EINVAL
     assert L.qfs_height_reduced(0, None, None, 10, 7, None, None, 0, None) == qfs.QFS_OK
+
+
+def test_mfma_peak_argument_errors():
+    L = qfs.lib()
+    import ctypes
+    t = ctypes.c_double(0.0)
+    assert L.qfs_mfma_peak(0, None, ctypes.byref(t), None) == qfs.QFS_EINVAL
+    assert L.qfs_mfma_peak(100, None, ctypes.byref(t), None) == qfs.QFS_EINVAL

@@ -171,6 +171,13 @@ def test_height_reduced_workloads_against_oracle(qfs, name):
         bad.size, len(H), bad[:5], got[bad[:5]], H[bad[:5]])
 
 
+def test_mfma_peak_is_plausible(qfs):
+    # the measured int8 matrix-core rate lies below the nominal dense peak (5.0 POP/s)
+    say("mfma peak loop")
+    tops = qfs.mfma_peak(2000)
+    assert 500.0 < tops < 5000.0 * 1.05
+
+
 @pytest.mark.parametrize("p", [5, 7, 11])
 def test_height_reduced_paper_tables(qfs, p):
     F, H = paper_rows(p)

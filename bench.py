@@ -35,11 +35,11 @@ INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix peak, 5.0 POP/s
 TRAFFIC_SOURCES = ("qfs_batched.hip", "qfs_device.h", "qfs_common.h", "qfs_internal.h")
 TRAFFIC = {
     "workload": "p7_batch65536",
-    "sources_sha256": "0f8a19bf4b09435d126700f7be3eb1a3809caecf2460a4dc25c7b5265ea7f5a2",
-    "fetch_scale": 524288.0 / 262169.4375, "write_scale": 1.0,
+    "sources_sha256": "b358f9e5b5c5f9a016ea183fdac1e7c68bb2940c3790ed96cb60180973a93db8",
+    "fetch_scale": 524288.0 / 262167.8750, "write_scale": 1.0,
     "kernels": {  # kernel name -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
-        "k_deep<7, true>": (26706442.78, 17981367.93),
-        "k_deep<7, false>": (29629939.69, 13223031.07),
+        "k_deep<7, true>": (26552028.56, 17943772.93),
+        "k_deep<7, false>": (29629595.62, 13219495.84),
     },
     "profile": "profiles/k_deep7_p7_batch65536_counters.md",
 }

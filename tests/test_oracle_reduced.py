@@ -90,7 +90,6 @@ def test_reproduces_paper_heights(p):
         assert reduced.height(f, p) == h
 
 
-@pytest.mark.slow
 def test_reproduces_paper_heights_p11():
     for f, h in _paper_rows(11):
         assert reduced.height(f, 11) == h

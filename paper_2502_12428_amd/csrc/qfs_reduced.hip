@@ -25,13 +25,56 @@ struct RedGeo {
     static constexpr int LHA = (LH + 15) / 16 * 16, LFA = (LF + 15) / 16 * 16;
 };
 
+// The next exponent after (e1, e2, e3, e4) in descending lex order of a fixed
+// degree (the CNS rank grows by one).
+__device__ inline void cns_next(int &e1, int &e2, int &e3, int &e4)
+{
+    if (e3 > 0) {
+        --e3;
+        ++e4;
+    } else if (e2 > 0) {
+        --e2;
+        e3 = e4 + 1;
+        e4 = 0;
+    } else {
+        --e1;
+        e2 = e4 + 1;
+        e4 = 0;
+    }
+}
+
+// out[r] = sum over the taps t <= x_r of coef(t) in[rank(x_r - t)] mod MOD for the
+// positions r of degree n (taps packed e1 | e2 << 8 | e3 << 16 | coef << 24, a
+// quartic's exponents); each thread takes a contiguous run of positions and
+// steps through them with cns_next.
+template <int MOD>
+__device__ inline void mul_taps(int n, const uint8_t *in, uint8_t *out, const uint32_t *taps, int ntaps)
+{
+    const int len = (int)num_mono(n), per = (len + RED_NT - 1) / RED_NT;
+    const int r0 = threadIdx.x * per, r1 = min(len, r0 + per);
+    if (r0 >= r1) return;
+    int x1, x2, x3, x4;
+    cns_unrank(n, r0, x1, x2, x3, x4);
+    for (int r = r0; r < r1; ++r) {
+        int acc = 0;
+        for (int k = 0; k < ntaps; ++k) {
+            const uint32_t te = taps[k];
+            const int t1 = te & 255, t2 = (te >> 8) & 255, t3 = (te >> 16) & 255, t4 = 4 - t1 - t2 - t3;
+            if (x1 >= t1 && x2 >= t2 && x3 >= t3 && x4 >= t4)
+                acc += (int)(te >> 24) * in[cns_rank(x2 - t2, x3 - t3, x4 - t4)];
+        }
+        out[r] = (uint8_t)(acc % MOD);
+        cns_next(x1, x2, x3, x4);
+    }
+}
+
 template <int P>
 __global__ __launch_bounds__(RED_NT) void k_reduced(Stage1Args a)
 {
     using G = RedGeo<P>;
     constexpr int P2 = P * P, d = G::d;
     static_assert(G::LFA >= G::LG, "M shares the second F buffer");
-    __shared__ __align__(16) uint8_t f35[48], v_l[48], hb0[G::LHA], hb1[G::LHA], fb0[G::LFA], fb1[G::LFA];
+    __shared__ __align__(16) uint8_t f35[48], v_l[48], hb0[G::LHA], fb0[G::LFA], fb1[G::LFA];
     __shared__ uint32_t taps[35], vtaps[35], wsum[35];
     __shared__ int ntap, nvt, s_err, s_test;
     const int tid = threadIdx.x, lane = tid & 63, pi = prime_index(P);
@@ -41,10 +84,29 @@ __global__ __launch_bounds__(RED_NT) void k_reduced(Stage1Args a)
         if (tid < 35) f35[tid] = (uint8_t)(a.f[(size_t)surf * 35 + tid] % P);
         if (tid == 0) s_err = 0;
         __syncthreads();
-        // H = f^(p-2) mod p (degree 4(p-2)); F^p mod p^2 (degree 4p)
-        const uint8_t *H = fpow_mod_lds<P - 2, P>(f35, hb0, hb1, taps, &ntap);
-        uint8_t *Dl = fpow_mod_lds<P, P2>(f35, fb0, fb1, taps, &ntap);
-        uint8_t *M = Dl == fb0 ? fb1 : fb0;
+        // F^j mod p^2 for j = 1..p by multiplication with the nonzero terms of f
+        // (degree 4j); on the way H = F^(p-2) mod p = f^(p-2) mod p (degree 4(p-2))
+        if (tid < 64) {
+            const int n = compact_taps(f35, taps);
+            if (tid == 0) ntap = n;
+        }
+        if (tid < 35) fb0[tid] = f35[tid];
+        __syncthreads();
+        const int nt = ntap;
+        uint8_t *cur = fb0, *nxt = fb1;
+        if (P - 2 == 1 && tid < 35) hb0[tid] = f35[tid];
+        for (int j = 1; j < P; ++j) {
+            mul_taps<P2>(4 * (j + 1), cur, nxt, taps, nt);
+            __syncthreads();
+            uint8_t *t = cur;
+            cur = nxt;
+            nxt = t;
+            if (j + 1 == P - 2)
+                for (int r = tid; r < G::LH; r += RED_NT) hb0[r] = (uint8_t)(cur[r] % P);
+        }
+        const uint8_t *H = hb0;
+        uint8_t *Dl = cur;
+        uint8_t *M = nxt;
         // D = (F^p - sum_I a_I^p x^(pI)) / p mod p, in place (Algorithm 1 on f)
         for (int r = tid; r < G::LF; r += RED_NT) {
             int x1, x2, x3, x4;
@@ -68,35 +130,28 @@ __global__ __launch_bounds__(RED_NT) void k_reduced(Stage1Args a)
             }
             if (tid < 35) wsum[tid] = 0;
             __syncthreads();
-            const int nv = nvt;
-            for (int c = tid; c < G::LG; c += RED_NT) {
-                int x1, x2, x3, x4;
-                cns_unrank(d, c, x1, x2, x3, x4);
-                int acc = 0;
-                for (int t = 0; t < nv; ++t) {
-                    const uint32_t te = vtaps[t];
-                    const int t1 = te & 255, t2 = (te >> 8) & 255, t3 = (te >> 16) & 255, t4 = 4 - t1 - t2 - t3;
-                    if (x1 >= t1 && x2 >= t2 && x3 >= t3 && x4 >= t4)
-                        acc += (int)(te >> 24) * H[cns_rank(x2 - t2, x3 - t3, x4 - t4)];
-                }
-                M[c] = (uint8_t)(acc % P);
-            }
+            mul_taps<P>(d, H, M, vtaps, nvt);
             __syncthreads();
             // w[r'] = u(D M)[r'] = sum_c M[c] D[p r' + e - c] for the 35 quartic exponents r'
             unsigned w[35];
 #pragma unroll
             for (int q = 0; q < 35; ++q) w[q] = 0;
-            for (int c = tid; c < G::LG; c += RED_NT) {
-                const unsigned mc = M[c];
-                if (!mc) continue;
-                int c1, c2, c3, c4;
-                cns_unrank(d, c, c1, c2, c3, c4);
+            {
+                // a contiguous run of positions c per thread, stepped with cns_next
+                constexpr int per = (G::LG + RED_NT - 1) / RED_NT;
+                const int c0 = tid * per, cend = min(G::LG, c0 + per);
+                int c1 = 0, c2 = 0, c3 = 0, c4 = 0;
+                if (c0 < cend) cns_unrank(d, c0, c1, c2, c3, c4);
+                for (int c = c0; c < cend; ++c, cns_next(c1, c2, c3, c4)) {
+                    const unsigned mc = M[c];
+                    if (!mc) continue;
 #pragma unroll
-                for (int q = 0; q < 35; ++q) {
-                    const uint32_t rb = kB4.e[q];
-                    const int y1 = P * (int)(rb & 255u) + P - 1 - c1, y2 = P * (int)((rb >> 8) & 255u) + P - 1 - c2,
-                              y3 = P * (int)((rb >> 16) & 255u) + P - 1 - c3, y4 = P * (int)(rb >> 24) + P - 1 - c4;
-                    if (y1 >= 0 && y2 >= 0 && y3 >= 0 && y4 >= 0) w[q] += mc * Dl[cns_rank(y2, y3, y4)];
+                    for (int q = 0; q < 35; ++q) {
+                        const uint32_t rb = kB4.e[q];
+                        const int y1 = P * (int)(rb & 255u) + P - 1 - c1, y2 = P * (int)((rb >> 8) & 255u) + P - 1 - c2,
+                                  y3 = P * (int)((rb >> 16) & 255u) + P - 1 - c3, y4 = P * (int)(rb >> 24) + P - 1 - c4;
+                        if (y1 >= 0 && y2 >= 0 && y3 >= 0 && y4 >= 0) w[q] += mc * Dl[cns_rank(y2, y3, y4)];
+                    }
                 }
             }
 #pragma unroll

@@ -108,16 +108,20 @@ __global__ __launch_bounds__(RED_NT) void k_reduced(Stage1Args a)
         uint8_t *Dl = cur;
         uint8_t *M = nxt;
         // D = (F^p - sum_I a_I^p x^(pI)) / p mod p, in place (Algorithm 1 on f)
-        for (int r = tid; r < G::LF; r += RED_NT) {
-            int x1, x2, x3, x4;
-            cns_unrank(G::DF, r, x1, x2, x3, x4);
-            int val = Dl[r];
-            if (x1 % P == 0 && x2 % P == 0 && x3 % P == 0 && x4 % P == 0) {
-                val -= pow_p_mod_p2<P>(f35[cns_rank(x2 / P, x3 / P, x4 / P)]);
-                if (val < 0) val += P2;
+        {
+            constexpr int per = (G::LF + RED_NT - 1) / RED_NT;
+            const int r0 = tid * per, rend = min(G::LF, r0 + per);
+            int x1 = 0, x2 = 0, x3 = 0, x4 = 0;
+            if (r0 < rend) cns_unrank(G::DF, r0, x1, x2, x3, x4);
+            for (int r = r0; r < rend; ++r, cns_next(x1, x2, x3, x4)) {
+                int val = Dl[r];
+                if (x1 % P == 0 && x2 % P == 0 && x3 % P == 0 && x4 % P == 0) {
+                    val -= pow_p_mod_p2<P>(f35[cns_rank(x2 / P, x3 / P, x4 / P)]);
+                    if (val < 0) val += P2;
+                }
+                if (val % P) s_err = 1;
+                Dl[r] = (uint8_t)(val / P);
             }
-            if (val % P) s_err = 1;
-            Dl[r] = (uint8_t)(val / P);
         }
         if (tid < 35) v_l[tid] = f35[tid];
         __syncthreads();

@@ -128,6 +128,37 @@ def cpu_model():
     return None
 
 
+def census(args, np, torch, qfs, workloads):
+    """Height census (the paper's random search, Section 7): heights of --census-n quartics with
+    coefficients uniform in F_p, from qfs_height_reduced in chunks, against the heuristic that a
+    random quartic has height >= k with probability about p^-(k-1).  The first 4,096 heights are
+    also computed by qfs_height (the int8-MFMA path) and compared."""
+    p, n, chunk = args.census, args.census_n, 1 << 18
+    hist = np.zeros(12, dtype=np.int64)  # 0: infinite, 1..10: heights, 11: per-surface errors
+    agree, t_gpu = None, 0.0
+    for start in range(0, n, chunk):
+        m = min(chunk, n - start)
+        f = torch.from_numpy(workloads.uniform(p, m, seed=1000 + start // chunk)).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = qfs.height_reduced(f, p)
+        torch.cuda.synchronize()
+        t_gpu += time.perf_counter() - t0
+        hh = h.cpu().numpy()
+        if start == 0:
+            k = min(m, 4096)
+            agree = bool(np.array_equal(hh[:k], qfs.height(f[:k], p).cpu().numpy()))
+        hist += np.bincount(np.where(hh < 0, 11, hh), minlength=12)[:12]
+    out = {"census": {
+        "p": p, "quartics": n, "data": "synthetic: coefficients uniform in F_p (seeded), the paper's random points",
+        "heights": {str(k): int(hist[k]) for k in range(1, 11)}, "infinite": int(hist[0]), "errors": int(hist[11]),
+        "observed_fraction": {str(k): float(hist[k]) / n for k in range(1, 11)},
+        "heuristic_fraction": {str(k): float(p) ** -(k - 1) * (1.0 - 1.0 / p) for k in range(1, 11)},
+        "ms": 1e3 * t_gpu, "quartics_per_s": n / t_gpu if t_gpu > 0 else None,
+        "agrees_with_qfs_height_on_first": agree}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +170,9 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=48)
     ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--no-reduced", action="store_true", help="skip timing qfs_height_reduced")
+    ap.add_argument("--census", type=int, default=0,
+                    help="p: instead of the benchmark, a height census of --census-n uniform quartics over F_p")
+    ap.add_argument("--census-n", type=int, default=1 << 20)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before the timed region, copy this many MiB device-to-device once: a plain copy "
                          "kernel of known size whose memory counters scale the profiler's byte counts")
@@ -153,6 +187,12 @@ def main():
 
     import paper_2502_12428_amd as qfs
     import workloads
+
+    if args.census:
+        if args.census not in (3, 5, 7, 11):
+            print("--census takes p in 3, 5, 7, 11", file=sys.stderr)
+            sys.exit(2)
+        return census(args, np, torch, qfs, workloads)
 
     F, P = workloads.CONFIGS[args.workload]()
     B = F.shape[0]

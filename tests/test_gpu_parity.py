@@ -178,6 +178,17 @@ def test_mfma_peak_is_plausible(qfs):
     assert 500.0 < tops < 5000.0 * 1.05
 
 
+def test_height_census_sample_against_oracle(qfs):
+    # a sample of the census workload (coefficients uniform in F_5): every height from the
+    # reduced path and from qfs_height equals the oracle's
+    F = workloads.uniform(5, 2048, seed=1000)
+    P = np.full(len(F), 5, dtype=np.int32)
+    say("census sample p=5 (2048 uniform quartics)")
+    want = fast.heights(F, P)
+    assert host(qfs.height_reduced(dev(F), 5)).tolist() == list(want)
+    assert host(qfs.height(dev(F), 5)).tolist() == list(want)
+
+
 @pytest.mark.parametrize("p", [5, 7, 11])
 def test_height_reduced_paper_tables(qfs, p):
     F, H = paper_rows(p)

@@ -43,25 +43,49 @@ __device__ inline void cns_next(int &e1, int &e2, int &e3, int &e4)
     }
 }
 
-// out[r] = sum over the taps t <= x_r of coef(t) in[rank(x_r - t)] mod MOD for the
-// positions r of degree n (taps packed e1 | e2 << 8 | e3 << 16 | coef << 24, a
-// quartic's exponents); each thread takes a contiguous run of positions and
-// steps through them with cns_next.
+// out[r] = sum over the quartic exponents t <= x_r of cf[t] in[rank(x_r - t)] mod MOD
+// for the positions r of degree n; cf holds the 35 coefficients of a quartic in CNS
+// order (the same for the whole block, read into scalar registers).  Each thread takes
+// a contiguous run of positions and steps through them with cns_next.  With
+// S = x2 + x3 + x4 and L = x3 + x4 the input rank is
+// tet3(S - (4 - t1)) + tri2(L - (t3 + t4)) + x4 - t4, so a position needs five values
+// of tet3 (they change with x1) and five of tri2 (they change with the line), and
+// x >= t componentwise is one borrow test on the packed exponent bytes.
 template <int MOD>
-__device__ inline void mul_taps(int n, const uint8_t *in, uint8_t *out, const uint32_t *taps, int ntaps)
+__device__ inline void mul_quartic(int n, const uint8_t *in, uint8_t *out, const uint8_t *cf35)
 {
+    constexpr B4Table b4 = make_b4();
+    int cf[35];
+#pragma unroll
+    for (int k = 0; k < 35; ++k) cf[k] = __builtin_amdgcn_readfirstlane((int)cf35[k]);
     const int len = (int)num_mono(n), per = (len + RED_NT - 1) / RED_NT;
     const int r0 = threadIdx.x * per, r1 = min(len, r0 + per);
     if (r0 >= r1) return;
     int x1, x2, x3, x4;
     cns_unrank(n, r0, x1, x2, x3, x4);
+    unsigned t1s[5], t2s[5];
+    int cS = -1, cL = -1;
     for (int r = r0; r < r1; ++r) {
+        const int S = x2 + x3 + x4, L = x3 + x4;
+        if (S != cS) {
+            cS = S;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) t1s[k] = tet3((unsigned)(S - k));
+        }
+        if (L != cL) {
+            cL = L;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) t2s[k] = tri2((unsigned)(L - k));
+        }
+        // byte i holds 0x80 + x_i: subtracting t leaves the top bit set iff x_i >= t_i
+        const uint32_t xp = ((uint32_t)x1 | (uint32_t)x2 << 8 | (uint32_t)x3 << 16 | (uint32_t)x4 << 24) | 0x80808080u;
         int acc = 0;
-        for (int k = 0; k < ntaps; ++k) {
-            const uint32_t te = taps[k];
-            const int t1 = te & 255, t2 = (te >> 8) & 255, t3 = (te >> 16) & 255, t4 = 4 - t1 - t2 - t3;
-            if (x1 >= t1 && x2 >= t2 && x3 >= t3 && x4 >= t4)
-                acc += (int)(te >> 24) * in[cns_rank(x2 - t2, x3 - t3, x4 - t4)];
+#pragma unroll
+        for (int k = 0; k < 35; ++k) {
+            constexpr uint32_t H = 0x80808080u;
+            const uint32_t te = b4.e[k];
+            const int t1 = (int)(te & 255u), t3 = (int)((te >> 16) & 255u), t4 = (int)(te >> 24);
+            if (cf[k] != 0 && ((xp - te) & H) == H) acc += cf[k] * in[t1s[4 - t1] + t2s[t3 + t4] + (unsigned)(x4 - t4)];
         }
         out[r] = (uint8_t)(acc % MOD);
         cns_next(x1, x2, x3, x4);
@@ -75,8 +99,8 @@ __global__ __launch_bounds__(RED_NT) void k_reduced(Stage1Args a)
     constexpr int P2 = P * P, d = G::d;
     static_assert(G::LFA >= G::LG, "M shares the second F buffer");
     __shared__ __align__(16) uint8_t f35[48], v_l[48], hb0[G::LHA], fb0[G::LFA], fb1[G::LFA];
-    __shared__ uint32_t taps[35], vtaps[35], wsum[35];
-    __shared__ int ntap, nvt, s_err, s_test;
+    __shared__ uint32_t wsum[35];
+    __shared__ int s_err, s_test;
     const int tid = threadIdx.x, lane = tid & 63, pi = prime_index(P);
     const int count = a.counters[CNT_COUNT + pi];
     for (int pos = blockIdx.x; pos < count; pos += gridDim.x) {
@@ -84,19 +108,14 @@ __global__ __launch_bounds__(RED_NT) void k_reduced(Stage1Args a)
         if (tid < 35) f35[tid] = (uint8_t)(a.f[(size_t)surf * 35 + tid] % P);
         if (tid == 0) s_err = 0;
         __syncthreads();
-        // F^j mod p^2 for j = 1..p by multiplication with the nonzero terms of f
-        // (degree 4j); on the way H = F^(p-2) mod p = f^(p-2) mod p (degree 4(p-2))
-        if (tid < 64) {
-            const int n = compact_taps(f35, taps);
-            if (tid == 0) ntap = n;
-        }
+        // F^j mod p^2 for j = 1..p by multiplication with f (degree 4j); on the way
+        // H = F^(p-2) mod p = f^(p-2) mod p (degree 4(p-2))
         if (tid < 35) fb0[tid] = f35[tid];
         __syncthreads();
-        const int nt = ntap;
         uint8_t *cur = fb0, *nxt = fb1;
         if (P - 2 == 1 && tid < 35) hb0[tid] = f35[tid];
         for (int j = 1; j < P; ++j) {
-            mul_taps<P2>(4 * (j + 1), cur, nxt, taps, nt);
+            mul_quartic<P2>(4 * (j + 1), cur, nxt, f35);
             __syncthreads();
             uint8_t *t = cur;
             cur = nxt;
@@ -127,21 +146,19 @@ __global__ __launch_bounds__(RED_NT) void k_reduced(Stage1Args a)
         __syncthreads();
         int h = 0;
         for (int k = 2; k <= a.bound; ++k) {
-            // M = H v (degree 4(p-1)), from the nonzero terms of v
-            if (tid < 64) {
-                const int n = compact_taps(v_l, vtaps);
-                if (tid == 0) nvt = n;
-            }
+            // M = H v (degree 4(p-1))
             if (tid < 35) wsum[tid] = 0;
+            mul_quartic<P>(d, H, M, v_l);
             __syncthreads();
-            mul_taps<P>(d, H, M, vtaps, nvt);
-            __syncthreads();
-            // w[r'] = u(D M)[r'] = sum_c M[c] D[p r' + e - c] for the 35 quartic exponents r'
+            // w[r'] = u(D M)[r'] = sum_c M[c] D[p r' + e - c] for the 35 quartic exponents r'.
+            // The index y = p r' + e - c is nonnegative iff floor(c_i / p) <= r'_i (a borrow
+            // test on packed bytes), and its rank is A[r'2 + r'3 + r'4] + B[r'3 + r'4] + p r'4 + p - 1 - c4
+            // with A[s] = tet3(p s + 3(p-1) - (c2 + c3 + c4)) and B[l] = tri2(p l + 2(p-1) - (c3 + c4)).
             unsigned w[35];
 #pragma unroll
             for (int q = 0; q < 35; ++q) w[q] = 0;
             {
-                // a contiguous run of positions c per thread, stepped with cns_next
+                constexpr B4Table b4 = make_b4();
                 constexpr int per = (G::LG + RED_NT - 1) / RED_NT;
                 const int c0 = tid * per, cend = min(G::LG, c0 + per);
                 int c1 = 0, c2 = 0, c3 = 0, c4 = 0;
@@ -149,12 +166,22 @@ __global__ __launch_bounds__(RED_NT) void k_reduced(Stage1Args a)
                 for (int c = c0; c < cend; ++c, cns_next(c1, c2, c3, c4)) {
                     const unsigned mc = M[c];
                     if (!mc) continue;
+                    const uint32_t kp = (uint32_t)(c1 / P) | (uint32_t)(c2 / P) << 8 | (uint32_t)(c3 / P) << 16 |
+                                        (uint32_t)(c4 / P) << 24;
+                    const int Sc = c2 + c3 + c4, Lc = c3 + c4;
+                    unsigned A[5], B[5];
+#pragma unroll
+                    for (int k = 0; k < 5; ++k) {
+                        A[k] = tet3((unsigned)(P * k + 3 * (P - 1) - Sc));
+                        B[k] = tri2((unsigned)(P * k + 2 * (P - 1) - Lc));
+                    }
+                    const unsigned base4 = (unsigned)(P - 1 - c4);
 #pragma unroll
                     for (int q = 0; q < 35; ++q) {
-                        const uint32_t rb = kB4.e[q];
-                        const int y1 = P * (int)(rb & 255u) + P - 1 - c1, y2 = P * (int)((rb >> 8) & 255u) + P - 1 - c2,
-                                  y3 = P * (int)((rb >> 16) & 255u) + P - 1 - c3, y4 = P * (int)(rb >> 24) + P - 1 - c4;
-                        if (y1 >= 0 && y2 >= 0 && y3 >= 0 && y4 >= 0) w[q] += mc * Dl[cns_rank(y2, y3, y4)];
+                        constexpr uint32_t H8 = 0x80808080u;
+                        const uint32_t rb = b4.e[q];
+                        const int r2 = (int)((rb >> 8) & 255u), r3 = (int)((rb >> 16) & 255u), r4 = (int)(rb >> 24);
+                        if ((((rb | H8) - kp) & H8) == H8) w[q] += mc * Dl[A[r2 + r3 + r4] + B[r3 + r4] + (unsigned)(P * r4) + base4];
                     }
                 }
             }
@@ -190,17 +217,32 @@ __global__ __launch_bounds__(RED_NT) void k_reduced(Stage1Args a)
     }
 }
 
+// The kernel walks its queue with a grid stride, so workgroups beyond those that fit
+// on the device at once would start only after others have finished: the grid is
+// at most the resident count.
+template <int P>
+static hipError_t launch_reduced_p(const Stage1Args &a, int nwg, hipStream_t s)
+{
+    int dev = 0, ncu = 0, per_cu = 0;
+    hipError_t e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_reduced<P>, RED_NT, 0)) != hipSuccess) return e;
+    if (per_cu > 0 && ncu > 0 && nwg > ncu * per_cu) nwg = ncu * per_cu;
+    hipLaunchKernelGGL(k_reduced<P>, dim3(nwg), dim3(RED_NT), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduced(int p, const Stage1Args &a, int nwg, hipStream_t s)
 {
     if (a.batch <= 0 || nwg <= 0) return hipSuccess;
     switch (p) {
-    case 3: hipLaunchKernelGGL(k_reduced<3>, dim3(nwg), dim3(RED_NT), 0, s, a); break;
-    case 5: hipLaunchKernelGGL(k_reduced<5>, dim3(nwg), dim3(RED_NT), 0, s, a); break;
-    case 7: hipLaunchKernelGGL(k_reduced<7>, dim3(nwg), dim3(RED_NT), 0, s, a); break;
-    case 11: hipLaunchKernelGGL(k_reduced<11>, dim3(nwg), dim3(RED_NT), 0, s, a); break;
+    case 3: return launch_reduced_p<3>(a, nwg, s);
+    case 5: return launch_reduced_p<5>(a, nwg, s);
+    case 7: return launch_reduced_p<7>(a, nwg, s);
+    case 11: return launch_reduced_p<11>(a, nwg, s);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace qfs

@@ -36,10 +36,10 @@ TRAFFIC_SOURCES = ("qfs_batched.hip", "qfs_device.h", "qfs_common.h", "qfs_inter
 TRAFFIC = {
     "workload": "p7_batch65536",
     "sources_sha256": "b358f9e5b5c5f9a016ea183fdac1e7c68bb2940c3790ed96cb60180973a93db8",
-    "fetch_scale": 524288.0 / 262168.8125, "write_scale": 1.0,
+    "fetch_scale": 524288.0 / 262169.7500, "write_scale": 1.0,
     "kernels": {  # kernel name -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
-        "k_deep<7, true>": (26619035.64, 17944524.66),
-        "k_deep<7, false>": (29621972.09, 13217183.66),
+        "k_deep<7, true>": (26644303.72, 17944999.24),
+        "k_deep<7, false>": (29634458.94, 13217736.77),
     },
     "profile": "profiles/k_deep7_p7_batch65536_counters.md",
 }

@@ -16,7 +16,9 @@
 
 namespace qfs {
 
-constexpr int RED_NT = 256;
+// Threads per workgroup.  At p = 11 the LDS buffers allow three workgroups per compute
+// unit, so each takes more threads.
+__host__ __device__ constexpr int red_nt(int p) { return p == 11 ? 512 : 256; }
 
 template <int P>
 struct RedGeo {
@@ -51,14 +53,14 @@ __device__ inline void cns_next(int &e1, int &e2, int &e3, int &e4)
 // tet3(S - (4 - t1)) + tri2(L - (t3 + t4)) + x4 - t4, so a position needs five values
 // of tet3 (they change with x1) and five of tri2 (they change with the line), and
 // x >= t componentwise is one borrow test on the packed exponent bytes.
-template <int MOD>
+template <int MOD, int NT>
 __device__ inline void mul_quartic(int n, const uint8_t *in, uint8_t *out, const uint8_t *cf35)
 {
     constexpr B4Table b4 = make_b4();
     int cf[35];
 #pragma unroll
     for (int k = 0; k < 35; ++k) cf[k] = __builtin_amdgcn_readfirstlane((int)cf35[k]);
-    const int len = (int)num_mono(n), per = (len + RED_NT - 1) / RED_NT;
+    const int len = (int)num_mono(n), per = (len + NT - 1) / NT;
     const int r0 = threadIdx.x * per, r1 = min(len, r0 + per);
     if (r0 >= r1) return;
     int x1, x2, x3, x4;
@@ -93,9 +95,10 @@ __device__ inline void mul_quartic(int n, const uint8_t *in, uint8_t *out, const
 }
 
 template <int P>
-__global__ __launch_bounds__(RED_NT) void k_reduced(Stage1Args a)
+__global__ __launch_bounds__(red_nt(P)) void k_reduced(Stage1Args a)
 {
     using G = RedGeo<P>;
+    constexpr int NT = red_nt(P);
     constexpr int P2 = P * P, d = G::d;
     static_assert(G::LFA >= G::LG, "M shares the second F buffer");
     __shared__ __align__(16) uint8_t f35[48], v_l[48], hb0[G::LHA], fb0[G::LFA], fb1[G::LFA];
@@ -115,20 +118,20 @@ __global__ __launch_bounds__(RED_NT) void k_reduced(Stage1Args a)
         uint8_t *cur = fb0, *nxt = fb1;
         if (P - 2 == 1 && tid < 35) hb0[tid] = f35[tid];
         for (int j = 1; j < P; ++j) {
-            mul_quartic<P2>(4 * (j + 1), cur, nxt, f35);
+            mul_quartic<P2, NT>(4 * (j + 1), cur, nxt, f35);
             __syncthreads();
             uint8_t *t = cur;
             cur = nxt;
             nxt = t;
             if (j + 1 == P - 2)
-                for (int r = tid; r < G::LH; r += RED_NT) hb0[r] = (uint8_t)(cur[r] % P);
+                for (int r = tid; r < G::LH; r += NT) hb0[r] = (uint8_t)(cur[r] % P);
         }
         const uint8_t *H = hb0;
         uint8_t *Dl = cur;
         uint8_t *M = nxt;
         // D = (F^p - sum_I a_I^p x^(pI)) / p mod p, in place (Algorithm 1 on f)
         {
-            constexpr int per = (G::LF + RED_NT - 1) / RED_NT;
+            constexpr int per = (G::LF + NT - 1) / NT;
             const int r0 = tid * per, rend = min(G::LF, r0 + per);
             int x1 = 0, x2 = 0, x3 = 0, x4 = 0;
             if (r0 < rend) cns_unrank(G::DF, r0, x1, x2, x3, x4);
@@ -148,7 +151,7 @@ __global__ __launch_bounds__(RED_NT) void k_reduced(Stage1Args a)
         for (int k = 2; k <= a.bound; ++k) {
             // M = H v (degree 4(p-1))
             if (tid < 35) wsum[tid] = 0;
-            mul_quartic<P>(d, H, M, v_l);
+            mul_quartic<P, NT>(d, H, M, v_l);
             __syncthreads();
             // w[r'] = u(D M)[r'] = sum_c M[c] D[p r' + e - c] for the 35 quartic exponents r'.
             // The index y = p r' + e - c is nonnegative iff floor(c_i / p) <= r'_i (a borrow
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(RED_NT) void k_reduced(Stage1Args a)
             for (int q = 0; q < 35; ++q) w[q] = 0;
             {
                 constexpr B4Table b4 = make_b4();
-                constexpr int per = (G::LG + RED_NT - 1) / RED_NT;
+                constexpr int per = (G::LG + NT - 1) / NT;
                 const int c0 = tid * per, cend = min(G::LG, c0 + per);
                 int c1 = 0, c2 = 0, c3 = 0, c4 = 0;
                 if (c0 < cend) cns_unrank(d, c0, c1, c2, c3, c4);
@@ -227,9 +230,9 @@ static hipError_t launch_reduced_p(const Stage1Args &a, int nwg, hipStream_t s)
     hipError_t e;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_reduced<P>, RED_NT, 0)) != hipSuccess) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_reduced<P>, red_nt(P), 0)) != hipSuccess) return e;
     if (per_cu > 0 && ncu > 0 && nwg > ncu * per_cu) nwg = ncu * per_cu;
-    hipLaunchKernelGGL(k_reduced<P>, dim3(nwg), dim3(RED_NT), 0, s, a);
+    hipLaunchKernelGGL(k_reduced<P>, dim3(nwg), dim3(red_nt(P)), 0, s, a);
     return hipGetLastError();
 }
 

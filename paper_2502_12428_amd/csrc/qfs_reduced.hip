@@ -19,6 +19,10 @@ namespace qfs {
 // Threads per workgroup.  At p = 11 the LDS buffers allow three workgroups per compute
 // unit, so each takes more threads.
 __host__ __device__ constexpr int red_nt(int p) { return p == 11 ? 512 : 256; }
+// At p = 11 (few workgroups per compute unit) the inner sums run branch-free, so that
+// their LDS reads are in flight together; at p <= 7 skipping the terms that do not
+// apply is faster.
+__host__ __device__ constexpr bool red_branch_free(int p) { return p == 11; }
 
 template <int P>
 struct RedGeo {
@@ -53,7 +57,7 @@ __device__ inline void cns_next(int &e1, int &e2, int &e3, int &e4)
 // tet3(S - (4 - t1)) + tri2(L - (t3 + t4)) + x4 - t4, so a position needs five values
 // of tet3 (they change with x1) and five of tri2 (they change with the line), and
 // x >= t componentwise is one borrow test on the packed exponent bytes.
-template <int MOD, int NT>
+template <int MOD, int NT, bool BF>
 __device__ inline void mul_quartic(int n, const uint8_t *in, uint8_t *out, const uint8_t *cf35)
 {
     constexpr B4Table b4 = make_b4();
@@ -87,7 +91,13 @@ __device__ inline void mul_quartic(int n, const uint8_t *in, uint8_t *out, const
             constexpr uint32_t H = 0x80808080u;
             const uint32_t te = b4.e[k];
             const int t1 = (int)(te & 255u), t3 = (int)((te >> 16) & 255u), t4 = (int)(te >> 24);
-            if (cf[k] != 0 && ((xp - te) & H) == H) acc += cf[k] * in[t1s[4 - t1] + t2s[t3 + t4] + (unsigned)(x4 - t4)];
+            if constexpr (BF) {  // a term with x < t reads position 0 and adds zero
+                const bool ok = ((xp - te) & H) == H;
+                const unsigned idx = ok ? t1s[4 - t1] + t2s[t3 + t4] + (unsigned)(x4 - t4) : 0u;
+                acc += (ok ? cf[k] : 0) * (int)in[idx];
+            } else if (cf[k] != 0 && ((xp - te) & H) == H) {
+                acc += cf[k] * in[t1s[4 - t1] + t2s[t3 + t4] + (unsigned)(x4 - t4)];
+            }
         }
         out[r] = (uint8_t)(acc % MOD);
         cns_next(x1, x2, x3, x4);
@@ -99,6 +109,7 @@ __global__ __launch_bounds__(red_nt(P)) void k_reduced(Stage1Args a)
 {
     using G = RedGeo<P>;
     constexpr int NT = red_nt(P);
+    constexpr bool BF = red_branch_free(P);
     constexpr int P2 = P * P, d = G::d;
     static_assert(G::LFA >= G::LG, "M shares the second F buffer");
     __shared__ __align__(16) uint8_t f35[48], v_l[48], hb0[G::LHA], fb0[G::LFA], fb1[G::LFA];
@@ -118,7 +129,7 @@ __global__ __launch_bounds__(red_nt(P)) void k_reduced(Stage1Args a)
         uint8_t *cur = fb0, *nxt = fb1;
         if (P - 2 == 1 && tid < 35) hb0[tid] = f35[tid];
         for (int j = 1; j < P; ++j) {
-            mul_quartic<P2, NT>(4 * (j + 1), cur, nxt, f35);
+            mul_quartic<P2, NT, BF>(4 * (j + 1), cur, nxt, f35);
             __syncthreads();
             uint8_t *t = cur;
             cur = nxt;
@@ -151,7 +162,7 @@ __global__ __launch_bounds__(red_nt(P)) void k_reduced(Stage1Args a)
         for (int k = 2; k <= a.bound; ++k) {
             // M = H v (degree 4(p-1))
             if (tid < 35) wsum[tid] = 0;
-            mul_quartic<P, NT>(d, H, M, v_l);
+            mul_quartic<P, NT, BF>(d, H, M, v_l);
             __syncthreads();
             // w[r'] = u(D M)[r'] = sum_c M[c] D[p r' + e - c] for the 35 quartic exponents r'.
             // The index y = p r' + e - c is nonnegative iff floor(c_i / p) <= r'_i (a borrow
@@ -184,7 +195,13 @@ __global__ __launch_bounds__(red_nt(P)) void k_reduced(Stage1Args a)
                         constexpr uint32_t H8 = 0x80808080u;
                         const uint32_t rb = b4.e[q];
                         const int r2 = (int)((rb >> 8) & 255u), r3 = (int)((rb >> 16) & 255u), r4 = (int)(rb >> 24);
-                        if ((((rb | H8) - kp) & H8) == H8) w[q] += mc * Dl[A[r2 + r3 + r4] + B[r3 + r4] + (unsigned)(P * r4) + base4];
+                        if constexpr (BF) {
+                            const bool ok = (((rb | H8) - kp) & H8) == H8;
+                            const unsigned idx = ok ? A[r2 + r3 + r4] + B[r3 + r4] + (unsigned)(P * r4) + base4 : 0u;
+                            w[q] += (ok ? mc : 0u) * Dl[idx];
+                        } else if ((((rb | H8) - kp) & H8) == H8) {
+                            w[q] += mc * Dl[A[r2 + r3 + r4] + B[r3 + r4] + (unsigned)(P * r4) + base4];
+                        }
                     }
                 }
             }
